@@ -1,0 +1,173 @@
+/*
+ * cqr.h - C ABI of the MI355X coded-QR library.
+ *
+ * Coded QR after Nguyen, Weissburg & Jeong, "Coded Computing for
+ * Fault-Tolerant Parallel QR Decomposition" (arXiv 2311.11943).  The nodes of
+ * the paper's p_r x p_c processor grid are the blocks of one matrix held in the
+ * HBM of one GPU; a node failure is an erasure of the blocks it holds.
+ *
+ * Conventions (every entry point):
+ *   - Matrices are column-major FP64 with an explicit leading dimension.
+ *   - Matrix pointers are DEVICE pointers owned by the caller; the library never
+ *     allocates, frees or retains them.  Host pointers are marked "host".
+ *   - Calls that take a hipStream_t enqueue their work on that stream and return
+ *     without waiting for it (no host-device synchronisation, no allocation).
+ *   - Errors are returned as cqr_status; nothing is thrown or aborted.  When an
+ *     argument check fails (CQR_EINVAL, CQR_ENOTRECOVERABLE) nothing has been
+ *     enqueued and every buffer is untouched.
+ *   - A plan is immutable after creation and may be shared by streams, but
+ *     calls that touch the same matrices or workspace must be ordered by the
+ *     caller (one stream, or events).
+ *
+ * Shapes: A is m x n (m >= n), p_r | m, p_c | n, p_r | n.  Block height
+ * bs = m/p_r, block width bw = n/p_c, R block height hr = n/p_r.  The encoded
+ * matrix A~ has m' = m + K_v*bs rows and N = n + K_h*bw columns; R is n x N.
+ */
+#ifndef CQR_H
+#define CQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CQR_OK = 0,
+  CQR_EINVAL = 1,          /* bad shape, pointer, leading dimension or option */
+  CQR_ENOTRECOVERABLE = 2, /* more erased blocks in a block row/column than surviving checksums */
+  CQR_ESINGULAR = 3,       /* the small generator submatrix to invert is numerically singular */
+  CQR_EHIP = 4,            /* a HIP runtime call failed (launch, copy) */
+  CQR_ENOMEM = 5,          /* workspace too small / host allocation failed */
+  CQR_EBREAKDOWN = 6       /* panel Gram matrix not positive definite (rank-deficient input) */
+} cqr_status;
+
+typedef enum { CQR_OUT_OF_NODE = 0, CQR_IN_NODE = 1 } cqr_storage;
+
+/* Arithmetic of the trailing-update products (panel norms, R diagonals,
+ * recovery solve and post-orthogonalization stay FP64 in every mode). */
+typedef enum { CQR_FP64 = 0, CQR_TRAIL_FP32 = 1, CQR_TRAIL_BF16X3 = 2 } cqr_precision;
+
+typedef struct {
+  int64_t m, n;        /* A is m x n; the paper's problem is square (m == n) */
+  int32_t pr, pc;      /* simulated node grid */
+  int32_t kv, kh;      /* checksum block-rows (protect Q) / block-columns (protect R) */
+  int32_t storage;     /* cqr_storage: which blocks a node failure erases */
+  int32_t b;           /* panel width of the blocked Gram-Schmidt; b | n */
+  int32_t reproject;   /* 1: re-project each panel against all earlier Q columns
+                          before factoring it (default); 0: the paper's PBMGS */
+  int32_t precision;   /* cqr_precision */
+} cqr_config;
+
+typedef struct cqr_plan_s* cqr_plan;
+
+/*
+ * Create a plan (host only, no device work).
+ *   v_tilde (host, K_v x (p_r - K_v), row-major): the Unif(0,1) entries that the
+ *     Q-side generator construction draws; the plan forms
+ *     G~_v = [G~_1  V~] with G~_1 = -1/2 V~ V~^T  (construction of the Q-factor
+ *     checksum generator, out-of-node and in-node forms).  Ignored if K_v = 0.
+ *   gh (host, p_c x K_h, row-major): R-side generator (any MDS code, System
+ *     Model / R-factor protection); for in-node storage the plan zeroes entry
+ *     (k mod p_c, k) so checksum k excludes its storing column (In-Node
+ *     Systematic MDS construction).  Ignored if K_h = 0.
+ *   Requires K_v <= p_r/2 when K_v > 0 (post-orthogonalization construction),
+ *   b | n, b <= 128 * 2^j (recursive panel), m % p_r == n % p_c == n % p_r == 0.
+ * Returns CQR_EINVAL on any violated condition; *out is then NULL.
+ */
+cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, const double* gh,
+                                cqr_plan* out);
+void coded_qr_plan_destroy(cqr_plan plan);
+
+/* Copy the plan's generators to host buffers: gv (K_v x p_r, row-major),
+ * gh (p_c x K_h, row-major, exclusion zeros applied).  Either may be NULL. */
+cqr_status coded_qr_plan_generators(cqr_plan plan, double* gv, double* gh);
+
+/* Failures per grid row / column the plan's code tolerates (out-of-node: K;
+ * in-node: largest f with f + f*ceil(f/(p_r-f)) <= K, the theorem on the
+ * minimum in-node checksum count). */
+int32_t coded_qr_plan_ftol(cqr_plan plan);
+
+/* Bytes of device workspace coded_qr_factor needs (caller allocates). */
+size_t coded_qr_workspace_bytes(cqr_plan plan);
+
+/*
+ * Encode (System Model, encoding equation):
+ *   A~ = [[A, A G_h], [G_v A, G_v A G_h]],  G = G~ (x) I.
+ * At (device, m' x N, ld ldat >= m'): on entry A sits in At[0:m, 0:n]; on exit
+ * the checksum rows, checksum columns and corner are written.  A is not read
+ * outside At[0:m, 0:n].
+ */
+cqr_status coded_qr_encode(cqr_plan plan, double* At, int64_t ldat, hipStream_t stream);
+
+/*
+ * Factor panels [panel_begin, panel_end) of the blocked Gram-Schmidt (the
+ * paper's PBMGS run on A~, appendix algorithm PBMGS / BMGS): for panel k with
+ * columns [kb, (k+1)b):
+ *   optional re-projection  S = Q[:, :kb]^T P,  P -= Q[:, :kb] S,  R[:kb, panel] += S;
+ *   panel orthogonalisation with reorthogonalisation (two Cholesky-QR passes,
+ *     the block form of CGS2; each a column operation P <- P T);
+ *   trailing update over every column right of the panel, checksum columns
+ *     included:  R_bar = Qbar^T Q_t,  R[panel, right] = R_bar,  Q_t -= Qbar R_bar.
+ * At (device, m' x N, ldat): the iteration state Q^(t) (A~ on the first call);
+ * R (device, n x N, ldr): zeroed by this call when panel_begin == 0.
+ * ws (device, >= coded_qr_workspace_bytes bytes, 256-byte aligned).
+ * Calls may be split at any panel boundary (failures are injected between).
+ * Numerical breakdown (rank deficiency) is recorded in the workspace and read
+ * with coded_qr_ws_info.
+ */
+cqr_status coded_qr_factor(cqr_plan plan, double* At, int64_t ldat, double* R, int64_t ldr,
+                           int32_t panel_begin, int32_t panel_end, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Blocking: wait for `stream`, then return the breakdown flag stored in ws
+ * (0 = none, else 1 + the panel index of the first breakdown) in *info (host). */
+cqr_status coded_qr_ws_info(cqr_plan plan, const void* ws, hipStream_t stream, int32_t* info);
+
+/*
+ * Fail-stop failure simulation: set every block held by the listed nodes to NaN
+ * (System Model, failure model; a node loses its inputs and results).
+ * failed_ij (host, 2*nfailed int32): node coordinates (i, j).  Out-of-node
+ * storage: 0 <= i < p_r + K_v, 0 <= j < p_c + K_h (i >= p_r or j >= p_c name
+ * checksum nodes).  In-node: 0 <= i < p_r, 0 <= j < p_c; a node also holds the
+ * checksum blocks placed on it (Q-checksum row k on grid row k mod p_r,
+ * R-checksum column k on grid column k mod p_c).
+ */
+cqr_status coded_qr_erase(cqr_plan plan, double* Q, int64_t ldq, double* R, int64_t ldr,
+                          const int32_t* failed_ij, int32_t nfailed, hipStream_t stream);
+
+/*
+ * Recover every block held by the listed nodes from surviving blocks and
+ * checksums (recovery-overhead lemma, decoding equation): per affected block
+ * column of Q (vertical code, Q_2 = G_v Q_1 holds for all N columns) and per
+ * block row of R (horizontal code, R_2 = R_1 G_h), with F the erased data
+ * blocks and S the |F| lowest-index surviving checksums,
+ *   X_F = G_hat^{-1} (C_S - sum_{t not in F} g~_{S,t} X_t),   G_hat = G~[S, F],
+ * then lost checksum blocks are re-encoded.  The small solve runs on the host
+ * in FP64 (no device read-back); every output block is one linear combination
+ * of surviving blocks, written by one HIP pass.
+ * Returns CQR_ENOTRECOVERABLE (nothing enqueued) if a line has more erased
+ * data blocks than surviving checksums, CQR_ESINGULAR if G_hat is singular.
+ */
+cqr_status coded_qr_recover(cqr_plan plan, double* Q, int64_t ldq, double* R, int64_t ldr,
+                            const int32_t* failed_ij, int32_t nfailed, hipStream_t stream);
+
+/*
+ * Post-orthogonalization (theorem on low-cost post-orthogonalization):
+ *   Qpost = G_0 Q_1,  Bpost = G_0 B,  G_0 = [[I + G_1, V], [V^T, -I]] = G^_0 (x) I_bs,
+ * with Q_1 = Q[0:m, 0:n].  Q (device, ldq >= m), Qpost (device, m x n, ldqp >= m),
+ * B / Bpost (device, m x nrhs, ldb / ldbp >= m; may be NULL when nrhs == 0).
+ * Qpost may alias Q and Bpost may alias B (in-place).  Requires K_v > 0.
+ */
+cqr_status coded_qr_postorth(cqr_plan plan, const double* Q, int64_t ldq, double* Qpost, int64_t ldqp,
+                             const double* B, int64_t ldb, double* Bpost, int64_t ldbp, int32_t nrhs,
+                             hipStream_t stream);
+
+const char* coded_qr_status_string(cqr_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CQR_H */
