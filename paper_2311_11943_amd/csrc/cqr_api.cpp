@@ -1,0 +1,500 @@
+// C-ABI entry points of the coded-QR library (declared in include/cqr.h).
+// Host side: argument checks, the code construction, the failure bookkeeping
+// and the small FP64 solves of the decoder; all matrix work is enqueued as HIP
+// kernels on the caller's stream.
+#include "cqr.h"
+#include "cqr_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <set>
+#include <utility>
+#include <vector>
+
+using cqr::kLeaf;
+using cqr::kMaxGen;
+using cqr::kMaxGrid;
+using cqr::kMaxLine;
+using cqr::kMaxOut;
+using cqr::kTile;
+
+struct cqr_plan_s {
+  cqr_config cfg;
+  int64_t bs, bw, hr, mp, N;
+  int ftol;
+  std::vector<double> gv;   // K_v x p_r row-major:  [G~_1  V~]
+  std::vector<double> gh;   // p_c x K_h row-major
+  int64_t ncounters = 0, npart = 0, nS = 0;
+  size_t off_cnt = 0, off_part = 0, off_S = 0, off_W = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Minimum in-node checksum count for f failures with L = P data blocks
+// (theorem on the in-node lower bound): K = f + f * ceil(f / (P - f)).
+int k_min_in_node(int f, int P) { return f + f * ((f + (P - f) - 1) / (P - f)); }
+
+int tolerated_code(int K, int P, int storage) {
+  if (K == 0) return 0;
+  if (storage == CQR_OUT_OF_NODE) return K;
+  int best = 0;
+  for (int f = 1; f < P; ++f)
+    if (k_min_in_node(f, P) <= K) best = f;
+  return best;
+}
+
+// Failures per grid row/column both codes tolerate.
+int tolerated(const cqr_plan_s& p) {
+  int f = tolerated_code(p.cfg.kv, p.cfg.pr, p.cfg.storage);
+  if (p.cfg.kh > 0) f = std::min(f, tolerated_code(p.cfg.kh, p.cfg.pc, p.cfg.storage));
+  return f;
+}
+
+// Gauss-Jordan inverse with partial pivoting (n <= kMaxOut); false if singular.
+bool invert(std::vector<double> a, int n, std::vector<double>& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  double scale = 0.0;
+  for (double v : a) scale = std::max(scale, std::fabs(v));
+  if (!(scale > 0.0)) return false;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * n + c]) > std::fabs(a[piv * n + c])) piv = r;
+    if (!(std::fabs(a[piv * n + c]) > 1e-13 * scale)) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[c * n + k], a[piv * n + k]);
+        std::swap(inv[c * n + k], inv[piv * n + k]);
+      }
+    double d = a[c * n + c];
+    for (int k = 0; k < n; ++k) { a[c * n + k] /= d; inv[c * n + k] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = a[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) { a[r * n + k] -= f * a[c * n + k]; inv[r * n + k] -= f * inv[c * n + k]; }
+    }
+  }
+  return true;
+}
+
+// Blocks a failed node holds.  Q blocks are (I, J) on the (p_r+K_v) x (p_c+K_h)
+// block grid of A~; R blocks are (i, J) with i < p_r.
+void node_blocks(const cqr_plan_s& p, int i, int j, std::vector<std::pair<int, int>>& q,
+                 std::vector<std::pair<int, int>>& r) {
+  const int pr = p.cfg.pr, pc = p.cfg.pc, kv = p.cfg.kv, kh = p.cfg.kh;
+  if (p.cfg.storage == CQR_OUT_OF_NODE) {
+    q.push_back({i, j});
+    if (i < pr) r.push_back({i, j});
+    return;
+  }
+  std::vector<int> rows{i}, cols{j};
+  for (int k = 0; k < kv; ++k) if (k % pr == i) rows.push_back(pr + k);
+  for (int k = 0; k < kh; ++k) if (k % pc == j) cols.push_back(pc + k);
+  for (int I : rows) for (int J : cols) q.push_back({I, J});
+  for (int J : cols) r.push_back({i, J});
+}
+
+cqr_status check_nodes(const cqr_plan_s& p, const int32_t* ij, int32_t nf) {
+  if (nf < 0 || (nf > 0 && !ij)) return CQR_EINVAL;
+  for (int f = 0; f < nf; ++f) {
+    int i = ij[2 * f], j = ij[2 * f + 1];
+    if (p.cfg.storage == CQR_OUT_OF_NODE) {
+      if (i < 0 || j < 0 || i >= p.cfg.pr + p.cfg.kv || j >= p.cfg.pc + p.cfg.kh) return CQR_EINVAL;
+    } else if (i < 0 || j < 0 || i >= p.cfg.pr || j >= p.cfg.pc) {
+      return CQR_EINVAL;
+    }
+  }
+  return CQR_OK;
+}
+
+// One decode job: a code line with `ndata` data blocks and `nchk` checksum
+// blocks, chk_k = sum_t gen[k][t] data_t.  Produces the launch descriptors.
+struct LineJob {
+  std::vector<int> lost_d, lost_c;
+};
+
+cqr_status plan_line(const std::vector<double>& gen, int ndata, int nchk, const LineJob& job,
+                     std::vector<int>& srcs, std::vector<int>& outs, std::vector<double>& coef) {
+  // Block index convention: data t -> t, checksum k -> ndata + k.
+  const auto& F = job.lost_d;
+  const auto& CF = job.lost_c;
+  std::vector<int> surv;
+  for (int k = 0; k < nchk; ++k)
+    if (std::find(CF.begin(), CF.end(), k) == CF.end()) surv.push_back(k);
+  const int f = (int)F.size();
+  if ((int)surv.size() < f) return CQR_ENOTRECOVERABLE;
+  std::vector<int> S(surv.begin(), surv.begin() + f);
+  std::vector<int> keep;
+  for (int t = 0; t < ndata; ++t)
+    if (std::find(F.begin(), F.end(), t) == F.end()) keep.push_back(t);
+  // sources: surviving data blocks, then the used checksums
+  srcs = keep;
+  for (int k : S) srcs.push_back(ndata + k);
+  const int ns = (int)srcs.size();
+  // coefficient rows of the recovered data blocks over all ndata+nchk slots
+  std::vector<std::vector<double>> xrow(ndata, std::vector<double>(ndata + nchk, 0.0));
+  for (int t : keep) xrow[t][t] = 1.0;
+  if (f > 0) {
+    std::vector<double> gh((size_t)f * f), ginv;
+    for (int a = 0; a < f; ++a)
+      for (int b = 0; b < f; ++b) gh[a * f + b] = gen[(size_t)S[a] * ndata + F[b]];
+    if (!invert(gh, f, ginv)) return CQR_ESINGULAR;
+    // X_F = Ginv (C_S - sum_{t in keep} gen[S, t] X_t)
+    for (int a = 0; a < f; ++a) {
+      auto& row = xrow[F[a]];
+      for (int b = 0; b < f; ++b) {
+        double gi = ginv[a * f + b];
+        row[ndata + S[b]] += gi;
+        for (int t : keep) row[t] -= gi * gen[(size_t)S[b] * ndata + t];
+      }
+    }
+  }
+  outs.clear();
+  coef.clear();
+  auto push = [&](int slot, const std::vector<double>& full) {
+    outs.push_back(slot);
+    for (int s = 0; s < ns; ++s) coef.push_back(full[srcs[s]]);
+  };
+  for (int t : F) push(t, xrow[t]);
+  for (int k : CF) {
+    std::vector<double> full(ndata + nchk, 0.0);
+    for (int t = 0; t < ndata; ++t) {
+      double g = gen[(size_t)k * ndata + t];
+      for (int s = 0; s < ndata + nchk; ++s) full[s] += g * xrow[t][s];
+    }
+    push(ndata + k, full);
+  }
+  return CQR_OK;
+}
+
+cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws) {
+  char* b = static_cast<char*>(ws);
+  cqr::Scratch s;
+  s.info = reinterpret_cast<int*>(b);
+  s.counters = reinterpret_cast<int*>(b + p.off_cnt);
+  s.ncounters = (int)p.ncounters;
+  s.part = reinterpret_cast<double*>(b + p.off_part);
+  s.npart = p.npart;
+  s.S = reinterpret_cast<double*>(b + p.off_S);
+  s.W = reinterpret_cast<double*>(b + p.off_W);
+  s.T = reinterpret_cast<double*>(b + p.off_T);
+  s.R1 = reinterpret_cast<double*>(b + p.off_R1);
+  return s;
+}
+
+cqr_status hip_status() { return hipGetLastError() == hipSuccess ? CQR_OK : CQR_EHIP; }
+
+// Panel of w columns starting at column c: leaves of <= kLeaf columns are
+// orthogonalised by two Cholesky-QR passes; wider panels are split, the right
+// part projected (twice) against the left part before being factored.
+void factor_panel(const cqr_plan_s& p, double* Q, int64_t ldq, double* R, int64_t ldr, int64_t c, int w,
+                  int panel, const cqr::Scratch& s, hipStream_t st) {
+  const int64_t mp = p.mp;
+  if (w <= kLeaf) {
+    double* P = Q + c * ldq;
+    cqr::launch_gram_chol(P, ldq, mp, w, 1, nullptr, 0, panel, s, st);
+    cqr::launch_apply(P, ldq, mp, w, s, st);
+    cqr::launch_gram_chol(P, ldq, mp, w, 2, R + c + c * ldr, ldr, panel, s, st);
+    cqr::launch_apply(P, ldq, mp, w, s, st);
+    return;
+  }
+  int h = (w / 2 + 15) / 16 * 16;
+  if (h >= w) h = w / 2;
+  factor_panel(p, Q, ldq, R, ldr, c, h, panel, s, st);
+  for (int pass = 0; pass < 2; ++pass) {
+    cqr::launch_tn(Q + c * ldq, ldq, Q + (c + h) * ldq, ldq, h, w - h, mp, s.S, h, R + c + (c + h) * ldr, ldr,
+                   s, st);
+    cqr::launch_nn_sub(Q + (c + h) * ldq, ldq, Q + c * ldq, ldq, s.S, h, mp, w - h, h, st);
+  }
+  factor_panel(p, Q, ldq, R, ldr, c + h, w - h, panel, s, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* coded_qr_status_string(cqr_status s) {
+  switch (s) {
+    case CQR_OK: return "ok";
+    case CQR_EINVAL: return "invalid argument";
+    case CQR_ENOTRECOVERABLE: return "not recoverable: more erased blocks than surviving checksums";
+    case CQR_ESINGULAR: return "singular generator submatrix";
+    case CQR_EHIP: return "HIP runtime error";
+    case CQR_ENOMEM: return "out of memory / workspace too small";
+    case CQR_EBREAKDOWN: return "panel breakdown (Gram matrix not positive definite)";
+  }
+  return "unknown status";
+}
+
+cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, const double* gh, cqr_plan* out) {
+  if (!out) return CQR_EINVAL;
+  *out = nullptr;
+  if (!cfg) return CQR_EINVAL;
+  const cqr_config& c = *cfg;
+  if (c.m <= 0 || c.n <= 0 || c.m < c.n || c.pr <= 0 || c.pc <= 0 || c.b <= 0) return CQR_EINVAL;
+  if (c.pr > kMaxGrid || c.pc > kMaxGrid || c.kv < 0 || c.kh < 0 || c.kv > kMaxGen || c.kh > kMaxGen)
+    return CQR_EINVAL;
+  if (c.pr + c.kv > kMaxLine || c.pc + c.kh > kMaxLine) return CQR_EINVAL;
+  if (c.m % c.pr || c.n % c.pc || c.n % c.pr || c.n % c.b) return CQR_EINVAL;
+  if (c.kv > 0 && 2 * c.kv > c.pr) return CQR_EINVAL;        // post-orthogonalization needs K_v <= p_r/2
+  if (c.kh > c.pc && c.storage == CQR_IN_NODE) return CQR_EINVAL;
+  if (c.storage != CQR_OUT_OF_NODE && c.storage != CQR_IN_NODE) return CQR_EINVAL;
+  if (c.precision != CQR_FP64) return CQR_EINVAL;
+  if (c.kv > 0 && !v_tilde) return CQR_EINVAL;
+  if (c.kh > 0 && !gh) return CQR_EINVAL;
+  if (c.m > (int64_t)1 << 31 || c.n > (int64_t)1 << 30) return CQR_EINVAL;
+
+  cqr_plan_s* p = new (std::nothrow) cqr_plan_s();
+  if (!p) return CQR_ENOMEM;
+  p->cfg = c;
+  p->bs = c.m / c.pr;
+  p->bw = c.n / c.pc;
+  p->hr = c.n / c.pr;
+  p->mp = c.m + c.kv * p->bs;
+  p->N = c.n + c.kh * p->bw;
+
+  // Q-side generator: G~_v = [G~_1  V~],  G~_1 = -1/2 V~ V~^T.
+  const int pr = c.pr, kv = c.kv, pc = c.pc, kh = c.kh;
+  p->gv.assign((size_t)kv * pr, 0.0);
+  for (int a = 0; a < kv; ++a) {
+    for (int t = 0; t < pr - kv; ++t) p->gv[a * pr + kv + t] = v_tilde[a * (pr - kv) + t];
+    for (int b2 = 0; b2 < kv; ++b2) {
+      double s = 0.0;
+      for (int t = 0; t < pr - kv; ++t) s += v_tilde[a * (pr - kv) + t] * v_tilde[b2 * (pr - kv) + t];
+      p->gv[a * pr + b2] = -0.5 * s;
+    }
+  }
+  // R-side generator; in-node storage excludes the storing column.
+  p->gh.assign((size_t)pc * kh, 0.0);
+  for (int t = 0; t < pc; ++t)
+    for (int k = 0; k < kh; ++k) p->gh[t * kh + k] = gh[t * kh + k];
+  if (c.storage == CQR_IN_NODE)
+    for (int k = 0; k < kh; ++k) p->gh[(k % pc) * kh + k] = 0.0;
+  p->ftol = tolerated(*p);
+
+  // Workspace layout.
+  const int64_t n = c.n, b = c.b, N = p->N;
+  int64_t maxTiles = 1;
+  auto tiles = [](int64_t M, int64_t Nc) { return ((M + kTile - 1) / kTile) * ((Nc + kTile - 1) / kTile); };
+  maxTiles = std::max(maxTiles, tiles(b, N - b));          // trailing update
+  maxTiles = std::max(maxTiles, tiles(n - b, b));          // re-projection
+  maxTiles = std::max(maxTiles, tiles(b, b));              // within-panel projection, Gram
+  p->ncounters = maxTiles + 1;
+  p->npart = std::max<int64_t>(1024, maxTiles);
+  p->nS = std::max<int64_t>(n * b, (int64_t)kLeaf * kLeaf);
+  size_t off = 256;
+  p->off_cnt = off;  off = align256(off + sizeof(int) * (size_t)p->ncounters);
+  p->off_part = off; off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
+  p->off_S = off;    off = align256(off + sizeof(double) * (size_t)p->nS);
+  p->off_W = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  p->off_T = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  p->off_R1 = off;   off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  p->ws_bytes = off;
+
+  *out = p;
+  return CQR_OK;
+}
+
+void coded_qr_plan_destroy(cqr_plan p) { delete p; }
+
+cqr_status coded_qr_plan_generators(cqr_plan p, double* gv, double* gh) {
+  if (!p) return CQR_EINVAL;
+  if (gv) std::memcpy(gv, p->gv.data(), p->gv.size() * sizeof(double));
+  if (gh) std::memcpy(gh, p->gh.data(), p->gh.size() * sizeof(double));
+  return CQR_OK;
+}
+
+int32_t coded_qr_plan_ftol(cqr_plan p) { return p ? p->ftol : -1; }
+
+size_t coded_qr_workspace_bytes(cqr_plan p) { return p ? p->ws_bytes : 0; }
+
+cqr_status coded_qr_encode(cqr_plan p, double* At, int64_t ldat, hipStream_t st) {
+  if (!p || !At || ldat < p->mp) return CQR_EINVAL;
+  if (p->cfg.kv == 0 && p->cfg.kh == 0) return CQR_OK;
+  cqr::EncodeArgs a{};
+  a.At = At; a.ld = ldat;
+  a.m = p->cfg.m; a.n = p->cfg.n; a.bs = p->bs; a.bw = p->bw;
+  a.pr = p->cfg.pr; a.pc = p->cfg.pc; a.kv = p->cfg.kv; a.kh = p->cfg.kh;
+  if (a.kv > 0) {
+    for (size_t e = 0; e < p->gv.size(); ++e) a.g[e] = p->gv[e];
+    cqr::launch_encode_rows(a, st);
+  }
+  if (a.kh > 0) {
+    for (int k = 0; k < a.kh; ++k)
+      for (int t = 0; t < a.pc; ++t) a.g[k * a.pc + t] = p->gh[t * a.kh + k];
+    cqr::launch_encode_cols(a, st);
+  }
+  return hip_status();
+}
+
+cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t pb, int32_t pe,
+                           void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!p || !Q || !R || !ws) return CQR_EINVAL;
+  const int64_t n = p->cfg.n, b = p->cfg.b, N = p->N, mp = p->mp;
+  const int npan = (int)(n / b);
+  if (ldq < mp || ldr < n || pb < 0 || pe > npan || pb > pe) return CQR_EINVAL;
+  if (ws_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255)) return CQR_ENOMEM;
+  cqr::Scratch s = scratch_of(*p, ws);
+  cqr::launch_zero_ints(s.counters, s.ncounters, st);
+  if (pb == 0) {
+    cqr::launch_zero_ints(s.info, 64, st);
+    cqr::launch_fill_zero(R, ldr, n, N, st);
+  }
+  for (int k = pb; k < pe; ++k) {
+    const int64_t c0 = (int64_t)k * b, c1 = c0 + b;
+    double* P = Q + c0 * ldq;
+    if (p->cfg.reproject && k > 0) {
+      // S = Q[:, :c0]^T P;  R[:c0, panel] += S;  P -= Q[:, :c0] S
+      cqr::launch_tn(Q, ldq, P, ldq, (int)c0, (int)b, mp, s.S, c0, R + c0 * ldr, ldr, s, st);
+      cqr::launch_nn_sub(P, ldq, Q, ldq, s.S, c0, mp, (int)b, (int)c0, st);
+    }
+    factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
+    if (c1 < N) {
+      // R_bar = Qbar^T Q_t -> R[panel, right];  Q_t -= Qbar R_bar
+      double* Rb = R + c0 + c1 * ldr;
+      cqr::launch_tn(P, ldq, Q + c1 * ldq, ldq, (int)b, (int)(N - c1), mp, Rb, ldr, nullptr, 0, s, st);
+      cqr::launch_nn_sub(Q + c1 * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(N - c1), (int)b, st);
+    }
+  }
+  return hip_status();
+}
+
+cqr_status coded_qr_ws_info(cqr_plan p, const void* ws, hipStream_t st, int32_t* info) {
+  if (!p || !ws || !info) return CQR_EINVAL;
+  if (hipStreamSynchronize(st) != hipSuccess) return CQR_EHIP;
+  int32_t v = 0;
+  if (hipMemcpy(&v, ws, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return CQR_EHIP;
+  *info = v;
+  return v ? CQR_EBREAKDOWN : CQR_OK;
+}
+
+cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,
+                          int32_t nf, hipStream_t st) {
+  if (!p || !Q || !R || ldq < p->mp || ldr < p->cfg.n) return CQR_EINVAL;
+  cqr_status cs = check_nodes(*p, ij, nf);
+  if (cs != CQR_OK) return cs;
+  std::set<std::pair<int, int>> qs, rs;
+  for (int f = 0; f < nf; ++f) {
+    std::vector<std::pair<int, int>> q, r;
+    node_blocks(*p, ij[2 * f], ij[2 * f + 1], q, r);
+    qs.insert(q.begin(), q.end());
+    rs.insert(r.begin(), r.end());
+  }
+  auto flush = [&](double* base, int64_t ld, int rows, int cols, std::vector<int64_t>& offs) {
+    for (size_t i = 0; i < offs.size(); i += 64) {
+      cqr::EraseArgs a{};
+      a.base = base; a.ld = ld; a.rows = rows; a.cols = cols;
+      a.nblk = (int)std::min<size_t>(64, offs.size() - i);
+      for (int k = 0; k < a.nblk; ++k) a.off[k] = offs[i + k];
+      cqr::launch_erase(a, st);
+    }
+  };
+  std::vector<int64_t> qo, ro;
+  for (auto& q : qs) qo.push_back(q.first * p->bs + (int64_t)q.second * p->bw * ldq);
+  for (auto& r : rs) ro.push_back(r.first * p->hr + (int64_t)r.second * p->bw * ldr);
+  flush(Q, ldq, (int)p->bs, (int)p->bw, qo);
+  flush(R, ldr, (int)p->hr, (int)p->bw, ro);
+  return hip_status();
+}
+
+cqr_status coded_qr_recover(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,
+                            int32_t nf, hipStream_t st) {
+  if (!p || !Q || !R || ldq < p->mp || ldr < p->cfg.n) return CQR_EINVAL;
+  cqr_status cs = check_nodes(*p, ij, nf);
+  if (cs != CQR_OK) return cs;
+  const int pr = p->cfg.pr, pc = p->cfg.pc, kv = p->cfg.kv, kh = p->cfg.kh;
+  std::set<std::pair<int, int>> qs, rs;
+  for (int f = 0; f < nf; ++f) {
+    std::vector<std::pair<int, int>> q, r;
+    node_blocks(*p, ij[2 * f], ij[2 * f + 1], q, r);
+    qs.insert(q.begin(), q.end());
+    rs.insert(r.begin(), r.end());
+  }
+  std::vector<cqr::LineArgs> launches;
+  // Q: every block column J, vertical code  chk_k = sum_t g~_v[k][t] data_t.
+  for (int J = 0; J < pc + kh; ++J) {
+    LineJob job;
+    for (int I = 0; I < pr; ++I) if (qs.count({I, J})) job.lost_d.push_back(I);
+    for (int k = 0; k < kv; ++k) if (qs.count({pr + k, J})) job.lost_c.push_back(k);
+    if (job.lost_d.empty() && job.lost_c.empty()) continue;
+    std::vector<int> srcs, outs;
+    std::vector<double> coef;
+    cs = plan_line(p->gv, pr, kv, job, srcs, outs, coef);
+    if (cs != CQR_OK) return cs;
+    auto off = [&](int slot) { return (int64_t)slot * p->bs + (int64_t)J * p->bw * ldq; };
+    const int ns = (int)srcs.size();
+    for (size_t o0 = 0; o0 < outs.size(); o0 += kMaxOut) {
+      cqr::LineArgs a{};
+      a.base = Q; a.ld = ldq; a.rows = (int)p->bs; a.cols = (int)p->bw;
+      a.nsrc = ns;
+      a.nout = (int)std::min<size_t>(kMaxOut, outs.size() - o0);
+      for (int s = 0; s < ns; ++s) a.src[s] = off(srcs[s]);
+      for (int o = 0; o < a.nout; ++o) {
+        a.dst[o] = off(outs[o0 + o]);
+        for (int s = 0; s < ns; ++s) a.coef[o][s] = coef[(o0 + o) * ns + s];
+      }
+      launches.push_back(a);
+    }
+  }
+  // R: every block row i, horizontal code  chk_k = sum_t g~_h[t][k] data_t.
+  if (!rs.empty()) {
+    std::vector<double> genT((size_t)kh * pc);
+    for (int k = 0; k < kh; ++k)
+      for (int t = 0; t < pc; ++t) genT[(size_t)k * pc + t] = p->gh[t * kh + k];
+    for (int i = 0; i < pr; ++i) {
+      LineJob job;
+      for (int J = 0; J < pc; ++J) if (rs.count({i, J})) job.lost_d.push_back(J);
+      for (int k = 0; k < kh; ++k) if (rs.count({i, pc + k})) job.lost_c.push_back(k);
+      if (job.lost_d.empty() && job.lost_c.empty()) continue;
+      std::vector<int> srcs, outs;
+      std::vector<double> coef;
+      cs = plan_line(genT, pc, kh, job, srcs, outs, coef);
+      if (cs != CQR_OK) return cs;
+      auto off = [&](int slot) { return (int64_t)i * p->hr + (int64_t)slot * p->bw * ldr; };
+      const int ns = (int)srcs.size();
+      for (size_t o0 = 0; o0 < outs.size(); o0 += kMaxOut) {
+        cqr::LineArgs a{};
+        a.base = R; a.ld = ldr; a.rows = (int)p->hr; a.cols = (int)p->bw;
+        a.nsrc = ns;
+        a.nout = (int)std::min<size_t>(kMaxOut, outs.size() - o0);
+        for (int s = 0; s < ns; ++s) a.src[s] = off(srcs[s]);
+        for (int o = 0; o < a.nout; ++o) {
+          a.dst[o] = off(outs[o0 + o]);
+          for (int s = 0; s < ns; ++s) a.coef[o][s] = coef[(o0 + o) * ns + s];
+        }
+        launches.push_back(a);
+      }
+    }
+  }
+  for (const auto& a : launches) cqr::launch_line(a, st);
+  return hip_status();
+}
+
+cqr_status coded_qr_postorth(cqr_plan p, const double* Q, int64_t ldq, double* Qpost, int64_t ldqp,
+                             const double* B, int64_t ldb, double* Bpost, int64_t ldbp, int32_t nrhs,
+                             hipStream_t st) {
+  if (!p || !Q || !Qpost || p->cfg.kv == 0 || nrhs < 0) return CQR_EINVAL;
+  const int64_t m = p->cfg.m;
+  if (ldq < m || ldqp < m) return CQR_EINVAL;
+  if (nrhs > 0 && (!B || !Bpost || ldb < m || ldbp < m)) return CQR_EINVAL;
+  cqr::PostArgs a{};
+  a.pr = p->cfg.pr; a.kv = p->cfg.kv; a.bs = p->bs;
+  for (size_t e = 0; e < p->gv.size(); ++e) a.gv[e] = p->gv[e];
+  a.src = Q; a.lds = ldq; a.dst = Qpost; a.ldd = ldqp; a.cols = p->cfg.n;
+  cqr::launch_postorth(a, st);
+  if (nrhs > 0) {
+    a.src = B; a.lds = ldb; a.dst = Bpost; a.ldd = ldbp; a.cols = nrhs;
+    cqr::launch_postorth(a, st);
+  }
+  return hip_status();
+}
+
+}  // extern "C"
