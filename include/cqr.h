@@ -15,9 +15,9 @@
  *   - Errors are returned as cqr_status; nothing is thrown or aborted.  When an
  *     argument check fails (CQR_EINVAL, CQR_ENOTRECOVERABLE) nothing has been
  *     enqueued and every buffer is untouched.
- *   - A plan is immutable after creation and may be shared by streams, but
- *     calls that touch the same matrices or workspace must be ordered by the
- *     caller (one stream, or events).
+ *   - A plan is immutable after creation (apart from the opt-in profiling
+ *     record) and may be shared by streams, but calls that touch the same
+ *     matrices or workspace must be ordered by the caller (one stream, or events).
  *
  * Shapes: A is m x n (m >= n), p_r | m, p_c | n, p_r | n.  Block height
  * bs = m/p_r, block width bw = n/p_c, R block height hr = n/p_r.  The encoded
@@ -73,8 +73,10 @@ typedef struct cqr_plan_s* cqr_plan;
  *     Model / R-factor protection); for in-node storage the plan zeroes entry
  *     (k mod p_c, k) so checksum k excludes its storing column (In-Node
  *     Systematic MDS construction).  Ignored if K_h = 0.
- *   Requires K_v <= p_r/2 when K_v > 0 (post-orthogonalization construction),
- *   b | n, b <= 128 * 2^j (recursive panel), m % p_r == n % p_c == n % p_r == 0.
+ *   Requires: K_v <= p_r/2 when K_v > 0 (post-orthogonalization construction);
+ *   m % p_r == n % p_c == n % p_r == 0; b | n; p_r, p_c <= 32; K_v, K_h <= 8;
+ *   p_r + K_v <= 32 and p_c + K_h <= 32; precision == CQR_FP64 (the other
+ *   values are reserved).
  * Returns CQR_EINVAL on any violated condition; *out is then NULL.
  */
 cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, const double* gh,
@@ -164,6 +166,26 @@ cqr_status coded_qr_recover(cqr_plan plan, double* Q, int64_t ldq, double* R, in
 cqr_status coded_qr_postorth(cqr_plan plan, const double* Q, int64_t ldq, double* Qpost, int64_t ldqp,
                              const double* B, int64_t ldb, double* Bpost, int64_t ldbp, int32_t nrhs,
                              hipStream_t stream);
+
+/*
+ * Per-phase timing (diagnostics).  While enabled, the plan records a HIP event
+ * pair on the call's stream around every kernel launch and remembers the
+ * phase, the algorithmic flops and the minimum HBM bytes of that launch.
+ * Enabling or disabling clears the record.  Reading waits for the recorded
+ * events (host-blocking).  Profiling makes the plan stateful: do not profile
+ * one plan from several host threads at once.
+ * Phases: 0 encode, 1 re-projection product (S = Q^T P), 2 re-projection update,
+ * 3 panel Gram + Cholesky, 4 panel transform (P <- P R^{-1}), 5 in-panel
+ * projection (split panels), 6 trailing product (R_bar = Qbar^T Q_t),
+ * 7 trailing update (Q_t -= Qbar R_bar), 8 recovery, 9 post-orthogonalization,
+ * 10 erase, 11 other (workspace/R initialisation).
+ * coded_qr_profile_read returns, for `phase`, the summed event time (ms), the
+ * number of launches and the summed flops / bytes (host outputs; may be NULL).
+ */
+#define CQR_NPHASES 12
+cqr_status coded_qr_profile_enable(cqr_plan plan, int32_t enable);
+cqr_status coded_qr_profile_read(cqr_plan plan, int32_t phase, double* total_ms, int64_t* launches,
+                                 double* flops, double* bytes);
 
 const char* coded_qr_status_string(cqr_status status);
 

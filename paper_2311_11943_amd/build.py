@@ -26,7 +26,10 @@ ARCH = os.environ.get("CQR_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]
 HIP_ONLY = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-munsafe-fp-atomics"]
+            "-munsafe-fp-atomics",
+            # MFMA accumulators in VGPRs: avoids per-iteration AGPR copies of
+            # loop-carried accumulators
+            "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _hipcc() -> str:

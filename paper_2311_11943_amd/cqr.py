@@ -24,7 +24,12 @@ EXPORTS = [
     "coded_qr_plan_create", "coded_qr_plan_destroy", "coded_qr_plan_generators", "coded_qr_plan_ftol",
     "coded_qr_workspace_bytes", "coded_qr_encode", "coded_qr_factor", "coded_qr_ws_info",
     "coded_qr_erase", "coded_qr_recover", "coded_qr_postorth", "coded_qr_status_string",
+    "coded_qr_profile_enable", "coded_qr_profile_read",
 ]
+
+PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram_chol", "panel_transform",
+          "inpanel_projection", "trailing_product", "trailing_update", "recover", "postorth", "erase",
+          "other"]
 
 
 class CqrError(RuntimeError):
@@ -60,6 +65,9 @@ def _load() -> ctypes.CDLL:
         "coded_qr_recover": (I32, [P, D, I64, D, I64, P, I32, V]),
         "coded_qr_postorth": (I32, [P, D, I64, D, I64, D, I64, D, I64, I32, V]),
         "coded_qr_status_string": (ctypes.c_char_p, [I32]),
+        "coded_qr_profile_enable": (I32, [P, I32]),
+        "coded_qr_profile_read": (I32, [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -91,8 +99,16 @@ def _ptr(t):
 
 
 def _ld(t) -> int:
-    """Leading dimension of a column-major (Fortran-ordered) 2-D tensor view."""
-    if t.dim() != 2 or t.stride(0) != 1:
+    """Leading dimension of a column-major (Fortran-ordered) 2-D tensor view.
+    Single-column tensors may carry any column stride; their ld is the row count."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    rows, cols = t.shape
+    if cols <= 1:
+        if rows > 1 and t.stride(0) != 1:
+            raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
+        return max(rows, 1)
+    if rows > 1 and t.stride(0) != 1:
         raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
     return max(t.stride(1), 1)
 
@@ -222,6 +238,18 @@ def coded_qr_postorth(plan: int, Q, Qpost, B=None, Bpost=None, stream=None) -> i
                                  ctypes.c_void_p(_stream(stream)))
 
 
+def coded_qr_profile_enable(plan: int, enable: bool) -> int:
+    return LIB.coded_qr_profile_enable(ctypes.c_void_p(plan), int(bool(enable)))
+
+
+def coded_qr_profile_read(plan: int, phase: int) -> dict:
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(LIB.coded_qr_profile_read(ctypes.c_void_p(plan), phase, ctypes.byref(ms), ctypes.byref(cnt),
+                                     ctypes.byref(fl), ctypes.byref(by)), "coded_qr_profile_read")
+    return {"ms": ms.value, "launches": cnt.value, "flops": fl.value, "bytes": by.value}
+
+
 # ---------------------------------------------------------------- convenience wrapper
 class CodedQR:
     """Plan + workspace on one device; methods raise CqrError on a bad status."""
@@ -248,6 +276,12 @@ class CodedQR:
     @property
     def ftol(self) -> int:
         return coded_qr_plan_ftol(self.plan)
+
+    def profile(self, enable: bool):
+        _check(coded_qr_profile_enable(self.plan, enable), "coded_qr_profile_enable")
+
+    def profile_report(self) -> dict:
+        return {name: coded_qr_profile_read(self.plan, i) for i, name in enumerate(PHASES)}
 
     def generators(self):
         return coded_qr_plan_generators(self.plan, self.cfg)

@@ -30,7 +30,15 @@ struct cqr_plan_s {
   std::vector<double> gh;   // p_c x K_h row-major
   int64_t ncounters = 0, npart = 0, nS = 0;
   size_t off_cnt = 0, off_part = 0, off_S = 0, off_W = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
+  // opt-in per-launch timing
+  struct Rec { int phase; hipEvent_t a, b; double flops, bytes; };
+  bool prof = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
 };
+
+enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
+             PH_TRAIL_NN, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER };
 
 namespace {
 
@@ -192,27 +200,76 @@ cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws) {
 
 cqr_status hip_status() { return hipGetLastError() == hipSuccess ? CQR_OK : CQR_EHIP; }
 
+hipEvent_t take_event(cqr_plan_s& p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` (one kernel) and, while profiling is on, bracket it with events.
+template <class F>
+void prof(cqr_plan_s& p, int phase, double flops, double bytes, hipStream_t st, F&& launch) {
+  if (!p.prof) {
+    launch();
+    return;
+  }
+  cqr_plan_s::Rec r{phase, take_event(p), take_event(p), flops, bytes};
+  if (r.a) (void)hipEventRecord(r.a, st);
+  launch();
+  if (r.b) (void)hipEventRecord(r.b, st);
+  p.recs.push_back(r);
+}
+
+void prof_clear(cqr_plan_s& p) {
+  for (auto& r : p.recs) {
+    if (r.a) p.pool.push_back(r.a);
+    if (r.b) p.pool.push_back(r.b);
+  }
+  p.recs.clear();
+}
+
+// Typed wrappers: flops and minimum bytes of each product.
+void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N,
+        int64_t K, double* C, int64_t ldc, double* C2, int64_t ldc2, const cqr::Scratch& s, hipStream_t st) {
+  double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N + (double)M * N);
+  prof(p, phase, fl, by, st, [&] { cqr::launch_tn(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s, st); });
+}
+
+void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64_t lda, const double* B,
+        int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st) {
+  double fl = 2.0 * M * N * (double)K, by = 8.0 * (2.0 * M * N + (double)M * K + (double)K * N);
+  prof(p, phase, fl, by, st, [&] { cqr::launch_nn_sub(C, ldc, A, lda, B, ldb, M, N, K, s, st); });
+}
+
+
 // Panel of w columns starting at column c: leaves of <= kLeaf columns are
 // orthogonalised by two Cholesky-QR passes; wider panels are split, the right
 // part projected (twice) against the left part before being factored.
-void factor_panel(const cqr_plan_s& p, double* Q, int64_t ldq, double* R, int64_t ldr, int64_t c, int w,
+void factor_panel(cqr_plan_s& p, double* Q, int64_t ldq, double* R, int64_t ldr, int64_t c, int w,
                   int panel, const cqr::Scratch& s, hipStream_t st) {
   const int64_t mp = p.mp;
   if (w <= kLeaf) {
     double* P = Q + c * ldq;
-    cqr::launch_gram_chol(P, ldq, mp, w, 1, nullptr, 0, panel, s, st);
-    cqr::launch_apply(P, ldq, mp, w, s, st);
-    cqr::launch_gram_chol(P, ldq, mp, w, 2, R + c + c * ldr, ldr, panel, s, st);
-    cqr::launch_apply(P, ldq, mp, w, s, st);
+    const double gfl = 2.0 * mp * w * w, gby = 8.0 * mp * w;
+    prof(p, PH_GRAM, gfl, gby, st, [&] { cqr::launch_gram_chol(P, ldq, mp, w, 1, nullptr, 0, panel, s, st); });
+    prof(p, PH_APPLY, gfl, 2 * gby, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
+    prof(p, PH_GRAM, gfl, gby, st,
+         [&] { cqr::launch_gram_chol(P, ldq, mp, w, 2, R + c + c * ldr, ldr, panel, s, st); });
+    prof(p, PH_APPLY, gfl, 2 * gby, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
     return;
   }
   int h = (w / 2 + 15) / 16 * 16;
   if (h >= w) h = w / 2;
   factor_panel(p, Q, ldq, R, ldr, c, h, panel, s, st);
   for (int pass = 0; pass < 2; ++pass) {
-    cqr::launch_tn(Q + c * ldq, ldq, Q + (c + h) * ldq, ldq, h, w - h, mp, s.S, h, R + c + (c + h) * ldr, ldr,
-                   s, st);
-    cqr::launch_nn_sub(Q + (c + h) * ldq, ldq, Q + c * ldq, ldq, s.S, h, mp, w - h, h, st);
+    tn(p, PH_INPANEL, Q + c * ldq, ldq, Q + (c + h) * ldq, ldq, h, w - h, mp, s.S, h, R + c + (c + h) * ldr,
+       ldr, s, st);
+    nn(p, PH_INPANEL, Q + (c + h) * ldq, ldq, Q + c * ldq, ldq, s.S, h, mp, w - h, h, s, st);
   }
   factor_panel(p, Q, ldq, R, ldr, c + h, w - h, panel, s, st);
 }
@@ -303,7 +360,42 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   return CQR_OK;
 }
 
-void coded_qr_plan_destroy(cqr_plan p) { delete p; }
+void coded_qr_plan_destroy(cqr_plan p) {
+  if (!p) return;
+  prof_clear(*p);
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+cqr_status coded_qr_profile_enable(cqr_plan p, int32_t enable) {
+  if (!p) return CQR_EINVAL;
+  prof_clear(*p);
+  p->prof = enable != 0;
+  return CQR_OK;
+}
+
+cqr_status coded_qr_profile_read(cqr_plan p, int32_t phase, double* total_ms, int64_t* launches, double* flops,
+                                 double* bytes) {
+  if (!p || phase < 0 || phase >= CQR_NPHASES) return CQR_EINVAL;
+  double ms = 0.0, fl = 0.0, by = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : p->recs) {
+    if (r.phase != phase) continue;
+    if (!r.a || !r.b) return CQR_EHIP;
+    if (hipEventSynchronize(r.b) != hipSuccess) return CQR_EHIP;
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return CQR_EHIP;
+    ms += e;
+    fl += r.flops;
+    by += r.bytes;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = cnt;
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  return CQR_OK;
+}
 
 cqr_status coded_qr_plan_generators(cqr_plan p, double* gv, double* gh) {
   if (!p) return CQR_EINVAL;
@@ -325,12 +417,16 @@ cqr_status coded_qr_encode(cqr_plan p, double* At, int64_t ldat, hipStream_t st)
   a.pr = p->cfg.pr; a.pc = p->cfg.pc; a.kv = p->cfg.kv; a.kh = p->cfg.kh;
   if (a.kv > 0) {
     for (size_t e = 0; e < p->gv.size(); ++e) a.g[e] = p->gv[e];
-    cqr::launch_encode_rows(a, st);
+    const double c = (double)a.kv * a.bs;
+    prof(*p, PH_ENCODE, 2.0 * a.kv * a.pr * a.bs * a.n, 8.0 * (a.m + c) * a.n, st,
+         [&] { cqr::launch_encode_rows(a, st); });
   }
   if (a.kh > 0) {
     for (int k = 0; k < a.kh; ++k)
       for (int t = 0; t < a.pc; ++t) a.g[k * a.pc + t] = p->gh[t * a.kh + k];
-    cqr::launch_encode_cols(a, st);
+    const double mpd = (double)p->mp;
+    prof(*p, PH_ENCODE, 2.0 * a.kh * a.pc * mpd * a.bw, 8.0 * mpd * (a.n + (double)a.kh * a.bw), st,
+         [&] { cqr::launch_encode_cols(a, st); });
   }
   return hip_status();
 }
@@ -343,25 +439,25 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
   if (ldq < mp || ldr < n || pb < 0 || pe > npan || pb > pe) return CQR_EINVAL;
   if (ws_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255)) return CQR_ENOMEM;
   cqr::Scratch s = scratch_of(*p, ws);
-  cqr::launch_zero_ints(s.counters, s.ncounters, st);
+  prof(*p, PH_OTHER, 0.0, 4.0 * s.ncounters, st, [&] { cqr::launch_zero_ints(s.counters, s.ncounters, st); });
   if (pb == 0) {
-    cqr::launch_zero_ints(s.info, 64, st);
-    cqr::launch_fill_zero(R, ldr, n, N, st);
+    prof(*p, PH_OTHER, 0.0, 256.0, st, [&] { cqr::launch_zero_ints(s.info, 64, st); });
+    prof(*p, PH_OTHER, 0.0, 8.0 * n * N, st, [&] { cqr::launch_fill_zero(R, ldr, n, N, st); });
   }
   for (int k = pb; k < pe; ++k) {
     const int64_t c0 = (int64_t)k * b, c1 = c0 + b;
     double* P = Q + c0 * ldq;
     if (p->cfg.reproject && k > 0) {
       // S = Q[:, :c0]^T P;  R[:c0, panel] += S;  P -= Q[:, :c0] S
-      cqr::launch_tn(Q, ldq, P, ldq, (int)c0, (int)b, mp, s.S, c0, R + c0 * ldr, ldr, s, st);
-      cqr::launch_nn_sub(P, ldq, Q, ldq, s.S, c0, mp, (int)b, (int)c0, st);
+      tn(*p, PH_REPROJ_TN, Q, ldq, P, ldq, (int)c0, (int)b, mp, s.S, c0, R + c0 * ldr, ldr, s, st);
+      nn(*p, PH_REPROJ_NN, P, ldq, Q, ldq, s.S, c0, mp, (int)b, (int)c0, s, st);
     }
     factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
     if (c1 < N) {
       // R_bar = Qbar^T Q_t -> R[panel, right];  Q_t -= Qbar R_bar
       double* Rb = R + c0 + c1 * ldr;
-      cqr::launch_tn(P, ldq, Q + c1 * ldq, ldq, (int)b, (int)(N - c1), mp, Rb, ldr, nullptr, 0, s, st);
-      cqr::launch_nn_sub(Q + c1 * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(N - c1), (int)b, st);
+      tn(*p, PH_TRAIL_TN, P, ldq, Q + c1 * ldq, ldq, (int)b, (int)(N - c1), mp, Rb, ldr, nullptr, 0, s, st);
+      nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(N - c1), (int)b, s, st);
     }
   }
   return hip_status();
@@ -394,7 +490,7 @@ cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t
       a.base = base; a.ld = ld; a.rows = rows; a.cols = cols;
       a.nblk = (int)std::min<size_t>(64, offs.size() - i);
       for (int k = 0; k < a.nblk; ++k) a.off[k] = offs[i + k];
-      cqr::launch_erase(a, st);
+      prof(*p, PH_ERASE, 0.0, 8.0 * rows * cols * a.nblk, st, [&] { cqr::launch_erase(a, st); });
     }
   };
   std::vector<int64_t> qo, ro;
@@ -474,7 +570,11 @@ cqr_status coded_qr_recover(cqr_plan p, double* Q, int64_t ldq, double* R, int64
       }
     }
   }
-  for (const auto& a : launches) cqr::launch_line(a, st);
+  for (const auto& a : launches) {
+    const double el = (double)a.rows * a.cols;
+    prof(*p, PH_RECOVER, 2.0 * el * a.nsrc * a.nout, 8.0 * el * (a.nsrc + a.nout), st,
+         [&] { cqr::launch_line(a, st); });
+  }
   return hip_status();
 }
 
@@ -488,11 +588,13 @@ cqr_status coded_qr_postorth(cqr_plan p, const double* Q, int64_t ldq, double* Q
   cqr::PostArgs a{};
   a.pr = p->cfg.pr; a.kv = p->cfg.kv; a.bs = p->bs;
   for (size_t e = 0; e < p->gv.size(); ++e) a.gv[e] = p->gv[e];
+  const double pr = p->cfg.pr, kv = p->cfg.kv;
+  const double fl_el = 2.0 * (kv * pr + (pr - kv) * (kv + 1)) / pr;   // flops per element
   a.src = Q; a.lds = ldq; a.dst = Qpost; a.ldd = ldqp; a.cols = p->cfg.n;
-  cqr::launch_postorth(a, st);
+  prof(*p, PH_POST, fl_el * m * a.cols, 16.0 * m * a.cols, st, [&] { cqr::launch_postorth(a, st); });
   if (nrhs > 0) {
     a.src = B; a.lds = ldb; a.dst = Bpost; a.ldd = ldbp; a.cols = nrhs;
-    cqr::launch_postorth(a, st);
+    prof(*p, PH_POST, fl_el * m * nrhs, 16.0 * m * nrhs, st, [&] { cqr::launch_postorth(a, st); });
   }
   return hip_status();
 }

@@ -79,7 +79,7 @@ void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s
 
 // C (M x N) -= A (M x K) B (K x N).
 void launch_nn_sub(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb,
-                   int64_t M, int N, int K, hipStream_t st);
+                   int64_t M, int N, int K, const Scratch& s, hipStream_t st);
 
 void launch_zero_ints(int* p, int n, hipStream_t st);
 void launch_fill_zero(double* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);
