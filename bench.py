@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip overhead/profile/oracle legs")
+    ap.add_argument("--lookahead", type=int, default=1, choices=(0, 1),
+                    help="1: overlap the next panel with the trailing update on a second stream")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -98,7 +100,7 @@ def main():
     w = WORKLOADS[args.workload]
     n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
     storage = cqr.CQR_IN_NODE if w["storage"] == "in" else cqr.CQR_OUT_OF_NODE
-    cfg = cqr.Config(n, n, pr, pr, K, K, b, storage)
+    cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead)
     v = synth.q_generator_draws(K, pr, args.seed)
     gh = synth.r_generator_draws(pr, K, args.seed)
     q = cqr.CodedQR(cfg, v, gh, dev)
@@ -157,6 +159,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "n": n, "grid": f"{pr}x{pr}", "b": b,
                    "K": K, "f_tol": ftol, "storage": w["storage"], "panel": "CholQR2 (block CGS2) + re-projection",
+                   "lookahead": args.lookahead,
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched],
                    "model_flops": F, "wall_s_timed": round(wall, 3)},
     }
@@ -191,7 +194,7 @@ def main():
         t_fac = timed(lambda: (enc(), fac()))  - t_enc
         t_post = timed(lambda: q.postorth(At, Qpost, B, Bpost))
         # uncoded: same library, K = 0
-        cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage)
+        cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead)
         qu = cqr.CodedQR(cu, None, None, dev)
         Au, Ru = qu.alloc()
 

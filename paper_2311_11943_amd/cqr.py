@@ -43,7 +43,8 @@ class cqr_config(ctypes.Structure):
                 ("pr", ctypes.c_int32), ("pc", ctypes.c_int32),
                 ("kv", ctypes.c_int32), ("kh", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("b", ctypes.c_int32),
-                ("reproject", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("reproject", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lookahead", ctypes.c_int32)]
 
 
 def _load() -> ctypes.CDLL:
@@ -139,10 +140,11 @@ class Config:
     storage: int = CQR_OUT_OF_NODE
     reproject: int = 1
     precision: int = CQR_FP64
+    lookahead: int = 1
 
     def c(self) -> cqr_config:
         return cqr_config(self.m, self.n, self.pr, self.pc, self.kv, self.kh, self.storage, self.b,
-                          self.reproject, self.precision)
+                          self.reproject, self.precision, self.lookahead)
 
     @property
     def bs(self):

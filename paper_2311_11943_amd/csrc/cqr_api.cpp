@@ -28,8 +28,13 @@ struct cqr_plan_s {
   int ftol;
   std::vector<double> gv;   // K_v x p_r row-major:  [G~_1  V~]
   std::vector<double> gh;   // p_c x K_h row-major
-  int64_t ncounters = 0, npart = 0, nS = 0;
-  size_t off_cnt = 0, off_part = 0, off_S = 0, off_W = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
+  int64_t npart = 0, nS = 0;
+  size_t off_part = 0, off_part2 = 0, off_S = 0, off_W = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
+  // lookahead: second stream and its two events, created on first use on the
+  // device current at that time
+  hipStream_t side = nullptr;
+  hipEvent_t ev_main = nullptr, ev_side = nullptr;
+  int side_dev = -1;
   // opt-in per-launch timing
   struct Rec { int phase; hipEvent_t a, b; double flops, bytes; };
   bool prof = false;
@@ -183,13 +188,13 @@ cqr_status plan_line(const std::vector<double>& gen, int ndata, int nchk, const 
   return CQR_OK;
 }
 
-cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws) {
+// Workspace views: `second` selects the split-product partials of the
+// lookahead stream (the two streams never share a scratch region).
+cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws, bool second = false) {
   char* b = static_cast<char*>(ws);
   cqr::Scratch s;
   s.info = reinterpret_cast<int*>(b);
-  s.counters = reinterpret_cast<int*>(b + p.off_cnt);
-  s.ncounters = (int)p.ncounters;
-  s.part = reinterpret_cast<double*>(b + p.off_part);
+  s.part = reinterpret_cast<double*>(b + (second ? p.off_part2 : p.off_part));
   s.npart = p.npart;
   s.S = reinterpret_cast<double*>(b + p.off_S);
   s.W = reinterpret_cast<double*>(b + p.off_W);
@@ -223,6 +228,32 @@ void prof(cqr_plan_s& p, int phase, double flops, double bytes, hipStream_t st, 
   launch();
   if (r.b) (void)hipEventRecord(r.b, st);
   p.recs.push_back(r);
+}
+
+void side_release(cqr_plan_s& p) {
+  if (p.ev_main) (void)hipEventDestroy(p.ev_main);
+  if (p.ev_side) (void)hipEventDestroy(p.ev_side);
+  if (p.side) (void)hipStreamDestroy(p.side);
+  p.side = nullptr;
+  p.ev_main = p.ev_side = nullptr;
+  p.side_dev = -1;
+}
+
+// The lookahead stream (default priority, no implicit synchronization with
+// the null stream) and its events on the current device.
+bool side_ready(cqr_plan_s& p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (p.side && p.side_dev == dev) return true;
+  side_release(p);
+  if (hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p.ev_main, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p.ev_side, hipEventDisableTiming) != hipSuccess) {
+    side_release(p);
+    return false;
+  }
+  p.side_dev = dev;
+  return true;
 }
 
 void prof_clear(cqr_plan_s& p) {
@@ -305,6 +336,7 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   if (c.kh > c.pc && c.storage == CQR_IN_NODE) return CQR_EINVAL;
   if (c.storage != CQR_OUT_OF_NODE && c.storage != CQR_IN_NODE) return CQR_EINVAL;
   if (c.precision != CQR_FP64) return CQR_EINVAL;
+  if (c.lookahead != 0 && c.lookahead != 1) return CQR_EINVAL;
   if (c.kv > 0 && !v_tilde) return CQR_EINVAL;
   if (c.kh > 0 && !gh) return CQR_EINVAL;
   if (c.m > (int64_t)1 << 31 || c.n > (int64_t)1 << 30) return CQR_EINVAL;
@@ -344,12 +376,11 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   maxTiles = std::max(maxTiles, tiles(b, N - b));          // trailing update
   maxTiles = std::max(maxTiles, tiles(n - b, b));          // re-projection
   maxTiles = std::max(maxTiles, tiles(b, b));              // within-panel projection, Gram
-  p->ncounters = maxTiles + 1;
   p->npart = std::max<int64_t>(1024, maxTiles);
   p->nS = std::max<int64_t>(n * b, (int64_t)kLeaf * kLeaf);
   size_t off = 256;
-  p->off_cnt = off;  off = align256(off + sizeof(int) * (size_t)p->ncounters);
-  p->off_part = off; off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
+  p->off_part = off;  off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
+  p->off_part2 = off; off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
   p->off_S = off;    off = align256(off + sizeof(double) * (size_t)p->nS);
   p->off_W = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
   p->off_T = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
@@ -364,6 +395,7 @@ void coded_qr_plan_destroy(cqr_plan p) {
   if (!p) return;
   prof_clear(*p);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  side_release(*p);
   delete p;
 }
 
@@ -439,11 +471,25 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
   if (ldq < mp || ldr < n || pb < 0 || pe > npan || pb > pe) return CQR_EINVAL;
   if (ws_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255)) return CQR_ENOMEM;
   cqr::Scratch s = scratch_of(*p, ws);
-  prof(*p, PH_OTHER, 0.0, 4.0 * s.ncounters, st, [&] { cqr::launch_zero_ints(s.counters, s.ncounters, st); });
+  const cqr::Scratch s2 = scratch_of(*p, ws, true);
   if (pb == 0) {
     prof(*p, PH_OTHER, 0.0, 256.0, st, [&] { cqr::launch_zero_ints(s.info, 64, st); });
     prof(*p, PH_OTHER, 0.0, 8.0 * n * N, st, [&] { cqr::launch_fill_zero(R, ldr, n, N, st); });
   }
+  const bool la = p->cfg.lookahead && pe - pb > 1 && side_ready(*p);
+  if (la) {
+    // the side stream starts after everything already queued on `st`
+    if (hipEventRecord(p->ev_main, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_main, 0) != hipSuccess)
+      return CQR_EHIP;
+  }
+  // Panel k's update of columns [from, N):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
+  auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
+    double* Rb = R + c0 + from * ldr;
+    const double* P = Q + c0 * ldq;
+    tn(*p, PH_TRAIL_TN, P, ldq, Q + from * ldq, ldq, (int)b, (int)(to - from), mp, Rb, ldr, nullptr, 0, sc, ss);
+    nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss);
+  };
+  bool side_pending = false;
   for (int k = pb; k < pe; ++k) {
     const int64_t c0 = (int64_t)k * b, c1 = c0 + b;
     double* P = Q + c0 * ldq;
@@ -453,13 +499,23 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       nn(*p, PH_REPROJ_NN, P, ldq, Q, ldq, s.S, c0, mp, (int)b, (int)c0, s, st);
     }
     factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
-    if (c1 < N) {
-      // R_bar = Qbar^T Q_t -> R[panel, right];  Q_t -= Qbar R_bar
-      double* Rb = R + c0 + c1 * ldr;
-      tn(*p, PH_TRAIL_TN, P, ldq, Q + c1 * ldq, ldq, (int)b, (int)(N - c1), mp, Rb, ldr, nullptr, 0, s, st);
-      nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(N - c1), (int)b, s, st);
+    if (c1 >= N) continue;
+    // columns right of panel k carry panel k-1's update from the side stream
+    if (side_pending && hipStreamWaitEvent(st, p->ev_side, 0) != hipSuccess) return CQR_EHIP;
+    side_pending = false;
+    if (la && k + 1 < pe && c1 + b < N) {
+      // lookahead: the next panel's columns now, the rest on the side stream
+      trail(c0, c1, c1 + b, s, st);
+      if (hipEventRecord(p->ev_main, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_main, 0) != hipSuccess)
+        return CQR_EHIP;
+      trail(c0, c1 + b, N, s2, p->side);
+      if (hipEventRecord(p->ev_side, p->side) != hipSuccess) return CQR_EHIP;
+      side_pending = true;
+    } else {
+      trail(c0, c1, N, s, st);
     }
   }
+  if (side_pending && hipStreamWaitEvent(st, p->ev_side, 0) != hipSuccess) return CQR_EHIP;
   return hip_status();
 }
 

@@ -53,8 +53,6 @@ struct PostArgs {
 // Scratch regions inside the caller's workspace (all device pointers).
 struct Scratch {
   int* info;          // [0]: breakdown flag (0 or 1 + panel)
-  int* counters;      // per-tile arrival counters, kept at zero between launches
-  int ncounters;
   double* part;       // split-K partial tiles
   int64_t npart;      // capacity in tiles (of kTile*kTile doubles)
   double* S;          // projection coefficients

@@ -120,6 +120,29 @@ def test_failures_recover_to_snapshot_and_final_matches(cqr, sid, n, pr, K, b, s
     q.close()
 
 
+@pytest.mark.parametrize("sid,n,pr,K,b", [("innode", 512, 8, 2, 64), ("ragged", 240, 4, 1, 16)])
+def test_lookahead_matches_single_stream(cqr, sid, n, pr, K, b):
+    """The second-stream schedule runs the same operations; only split-product
+    summation order may differ.  Both agree with the oracle."""
+    print(f"[case] lookahead {sid}", flush=True)
+    A, v, gh, lay = make_inputs(n, pr, K, b, "in" if sid == "innode" else "out", seed=7)
+    sched = synth.draw_schedule("random", n // b, pr, pr, 7, nfail=1)
+    out = {}
+    for la in (0, 1):
+        q = cqr.CodedQR(gpu_config(cqr, lay, b, lookahead=la), v, gh)
+        At, R, _, _ = q.run(_dev(cqr, A), sched)
+        torch.cuda.synchronize()
+        out[la] = (host(At), host(R))
+        assert q.info() == 0
+        q.close()
+    assert rel(out[1][1], out[0][1]) < 1e-13
+    assert np.abs(out[1][0] - out[0][0]).max() < 1e-13
+    ref = oc.run(oc.Problem(A, lay, v, gh, oc.FactorOptions(b, "icgs"), sched))
+    for la in (0, 1):
+        assert rel(out[la][1], ref["R"]) < 1e-11
+        assert np.abs(out[la][0] - ref["Q"]).max() < 1e-11
+
+
 def test_postorth_matches_oracle(cqr):
     n, pr, K, b = 256, 8, 4, 32
     A, v, gh, lay = make_inputs(n, pr, K, b, "out", seed=3)
