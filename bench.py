@@ -46,8 +46,39 @@ WORKLOADS = {
 }
 
 
+# Phases whose kernel is bound by FP64 MFMA throughput (products with one
+# 64-wide dimension and a long reduction: 16 flop per byte, above the
+# 78.6 TFLOP/s / 8 TB/s ridge); the rest are bound by HBM bytes.
+MFMA_PHASES = {"reproj_product", "reproj_update", "panel_gram", "inpanel_projection", "trailing_product"}
+KERNEL_OF = {
+    "encode": "encode_rows_kernel / encode_cols_kernel",
+    "reproj_product": "tn_lds_kernel<1>", "reproj_update": "nn_kernel<*, 1>", "panel_gram": "tn_lds_kernel<2>",
+    "panel_chol": "chol_kernel", "panel_transform": "apply_kernel", "inpanel_projection": "tn/nn <2>",
+    "trailing_product": "tn_lds_kernel<0>", "trailing_update": "nn1_kernel<0>",
+    "split_reduce": "tn_reduce_kernel / nn_reduce_kernel / gram_sum_kernel", "recover": "line_kernel",
+    "postorth": "postorth_kernel", "erase": "erase_kernel", "other": "zero_ints_kernel / fill_zero_kernel",
+}
+
+
 def model_flops(mp, n, d, b):
     return mp * (4.0 * n * n + 4.0 * n * d + 4.0 * n * b)
+
+
+def workload_inputs(name: str, ftol: int, seed: int = 0) -> dict:
+    """Seeded inputs of a workload: A, the right-hand side, the generator draws
+    and the failure schedule (shared with the full-size parity test).  ftol is
+    the code's failure tolerance per grid line (sizes reverse-diagonal storms)."""
+    w = WORKLOADS[name]
+    n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
+    return {
+        "A": synth.gaussian(n, n, seed),
+        "rhs": synth.gaussian(n, 1, seed + 1),
+        "v": synth.q_generator_draws(K, pr, seed),
+        "gh": synth.r_generator_draws(pr, K, seed),
+        # "random": nfail single-node events at independent random panels
+        # (events sharing a panel hit distinct grid rows and columns)
+        "schedule": synth.draw_schedule(w["kind"], n // b, pr, pr, seed, nfail=w["nfail"], every=16, f=ftol),
+    }
 
 
 def source_hash() -> str:
@@ -84,6 +115,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip overhead/profile/oracle legs")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, launch one plain copy kernel of 512 MiB (y = 2x) as the reference for "
+                         "HBM byte counters")
     ap.add_argument("--lookahead", type=int, default=1, choices=(0, 1),
                     help="1: overlap the next panel with the trailing update on a second stream")
     args = ap.parse_args()
@@ -105,10 +139,8 @@ def main():
     gh = synth.r_generator_draws(pr, K, args.seed)
     q = cqr.CodedQR(cfg, v, gh, dev)
     ftol = q.ftol
-    sched = synth.draw_schedule(w["kind"], cfg.npanels, pr, pr, args.seed, nfail=min(w["nfail"], ftol),
-                                every=16, f=ftol)
-    A_host = synth.gaussian(n, n, args.seed)
-    rhs_host = synth.gaussian(n, 1, args.seed + 1)
+    inp = workload_inputs(args.workload, ftol, args.seed)
+    A_host, rhs_host, sched = inp["A"], inp["rhs"], inp["schedule"]
     A = cqr.to_device_colmajor(A_host, dev)
     B = cqr.to_device_colmajor(rhs_host, dev)
     At, R = q.alloc()
@@ -229,23 +261,34 @@ def main():
         nrec = sum(r["launches"] for r in rep.values())
         rec_ms = rep["recover"]["ms"]
         out["overhead"]["T_recov_ms_per_event"] = round(rec_ms / max(len(sched), 1), 4)
+        # the single kernel (one phase = one kernel symbol) holding the most time
         dom = max((k for k in rep if rep[k]["launches"]), key=lambda k: rep[k]["ms"])
         r = rep[dom]
-        mfma = dom not in ("encode", "recover", "postorth", "erase", "other")
-        if mfma:
+        if dom in MFMA_PHASES:
             ach = r["flops"] / (r["ms"] * 1e-3) / 1e12
-            roof = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["fp64_mfma_tflops"],
-                    "unit": "TFLOP/s", "frac": round(ach / PEAK["fp64_mfma_tflops"], 4)}
+            roof = {"kernel": KERNEL_OF[dom], "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
+                    "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s",
+                    "frac": round(ach / PEAK["fp64_mfma_tflops"], 4)}
         else:
             ach = r["bytes"] / (r["ms"] * 1e-3) / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"],
-                    "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
+            roof = {"kernel": KERNEL_OF[dom], "phase": dom, "bound": "hbm", "achieved": round(ach, 1),
+                    "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
         roof["avg_launch_us"] = round(1e3 * r["ms"] / r["launches"], 3)
         roof["launches"] = r["launches"]
         roof["share_of_profiled_step"] = round(r["ms"] / sum(x["ms"] for x in rep.values()), 3)
         roof["traffic"] = traffic_record(dom, args.workload)
         roof["events_per_step"] = 2 * nrec
         out["roofline"] = roof
+
+    if args.calib_copy:
+        # reference for rocprofv3 FETCH_SIZE / WRITE_SIZE: reads and writes exactly 512 MiB each
+        xs = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        ys = torch.empty_like(xs)
+        torch.cuda.synchronize()
+        torch.mul(xs, 2.0, out=ys)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 8 * (64 << 20)
+        del xs, ys
 
     if not args.no_cpu_baseline:
         from oracle import coded_qr as oc

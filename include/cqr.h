@@ -173,25 +173,33 @@ cqr_status coded_qr_postorth(cqr_plan plan, const double* Q, int64_t ldq, double
 
 /*
  * Per-phase timing (diagnostics).  While enabled, the plan records a HIP event
- * pair on the call's stream around every kernel launch and remembers the
- * phase, the algorithmic flops and the minimum HBM bytes of that launch.
- * Enabling or disabling clears the record.  Reading waits for the recorded
- * events (host-blocking).  Profiling makes the plan stateful: do not profile
- * one plan from several host threads at once.
- * Phases: 0 encode, 1 re-projection product (S = Q^T P), 2 re-projection update,
- * 3 panel Gram + Cholesky, 4 panel transform (P <- P R^{-1}), 5 in-panel
- * projection (split panels), 6 trailing product (R_bar = Qbar^T Q_t),
- * 7 trailing update (Q_t -= Qbar R_bar), 8 recovery, 9 post-orthogonalization,
- * 10 erase, 11 other (workspace/R initialisation).
+ * pair around every kernel launch, on the stream that launch runs on, and
+ * remembers the phase, the algorithmic flops and the minimum HBM bytes of that
+ * launch; each record covers exactly one kernel.  Enabling or disabling clears
+ * the record.  Reading waits for the recorded events (host-blocking).
+ * Profiling makes the plan stateful: do not profile one plan from several host
+ * threads at once.
+ * Phases: 0 encode, 1 re-projection product (S = Q^T P), 2 re-projection update
+ * (P -= Q S), 3 panel Gram product (P^T P), 4 panel Cholesky factor and
+ * inverse, 5 panel transform (P <- P R^{-1}), 6 in-panel projection (split
+ * panels), 7 trailing product (R_bar = Qbar^T Q_t), 8 trailing update
+ * (Q_t -= Qbar R_bar), 9 reduction of split-product partial tiles, 10 recovery,
+ * 11 post-orthogonalization, 12 erase, 13 other (workspace/R initialisation).
  * coded_qr_profile_read returns, for `phase`, the summed event time (ms), the
  * number of launches and the summed flops / bytes (host outputs; may be NULL).
  */
-#define CQR_NPHASES 12
+#define CQR_NPHASES 14
 cqr_status coded_qr_profile_enable(cqr_plan plan, int32_t enable);
 cqr_status coded_qr_profile_read(cqr_plan plan, int32_t phase, double* total_ms, int64_t* launches,
                                  double* flops, double* bytes);
 
 const char* coded_qr_status_string(cqr_status status);
+
+/* Name of the HIP error behind the calling thread's most recent CQR_EHIP
+ * ("hipSuccess" if there was none).  Entry points that launch work first
+ * discard an error that other code left pending on the thread, so a CQR_EHIP
+ * always stems from the library's own HIP calls. */
+const char* coded_qr_hip_error_name(void);
 
 #ifdef __cplusplus
 }

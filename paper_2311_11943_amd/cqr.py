@@ -24,18 +24,19 @@ EXPORTS = [
     "coded_qr_plan_create", "coded_qr_plan_destroy", "coded_qr_plan_generators", "coded_qr_plan_ftol",
     "coded_qr_workspace_bytes", "coded_qr_encode", "coded_qr_factor", "coded_qr_ws_info",
     "coded_qr_erase", "coded_qr_recover", "coded_qr_postorth", "coded_qr_status_string",
-    "coded_qr_profile_enable", "coded_qr_profile_read",
+    "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name",
 ]
 
-PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram_chol", "panel_transform",
-          "inpanel_projection", "trailing_product", "trailing_update", "recover", "postorth", "erase",
-          "other"]
+PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram", "panel_chol", "panel_transform",
+          "inpanel_projection", "trailing_product", "trailing_update", "split_reduce", "recover", "postorth",
+          "erase", "other"]
 
 
 class CqrError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__(f"{where}: {status_string(status)} (status {status})")
+        detail = f", {hip_error_name()}" if status == CQR_EHIP else ""
+        super().__init__(f"{where}: {status_string(status)} (status {status}{detail})")
 
 
 class cqr_config(ctypes.Structure):
@@ -48,6 +49,10 @@ class cqr_config(ctypes.Structure):
 
 
 def _load() -> ctypes.CDLL:
+    # torch first: libcqr.so then binds to the HIP runtime torch has loaded.
+    # Loaded the other way round, the process would hold two HIP/HSA runtimes
+    # and the library's would find no device.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_11943_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
@@ -66,6 +71,7 @@ def _load() -> ctypes.CDLL:
         "coded_qr_recover": (I32, [P, D, I64, D, I64, P, I32, V]),
         "coded_qr_postorth": (I32, [P, D, I64, D, I64, D, I64, D, I64, I32, V]),
         "coded_qr_status_string": (ctypes.c_char_p, [I32]),
+        "coded_qr_hip_error_name": (ctypes.c_char_p, []),
         "coded_qr_profile_enable": (I32, [P, I32]),
         "coded_qr_profile_read": (I32, [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -82,6 +88,11 @@ LIB = _load()
 
 def status_string(status: int) -> str:
     return LIB.coded_qr_status_string(status).decode()
+
+
+def hip_error_name() -> str:
+    """HIP error behind this thread's most recent CQR_EHIP."""
+    return LIB.coded_qr_hip_error_name().decode()
 
 
 def _check(status: int, where: str):

@@ -42,8 +42,9 @@ struct cqr_plan_s {
   std::vector<hipEvent_t> pool;
 };
 
-enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
-             PH_TRAIL_NN, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER };
+enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_CHOL, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
+             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER };
+static_assert(PH_OTHER + 1 == CQR_NPHASES, "phase list and header disagree");
 
 namespace {
 
@@ -203,7 +204,22 @@ cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws, bool second = false) {
   return s;
 }
 
-cqr_status hip_status() { return hipGetLastError() == hipSuccess ? CQR_OK : CQR_EHIP; }
+// HIP error behind the calling thread's last CQR_EHIP.
+thread_local hipError_t t_hip_error = hipSuccess;
+
+cqr_status hip_fail(hipError_t e) {
+  t_hip_error = e;
+  return CQR_EHIP;
+}
+
+// Entry points that launch work first drop an error another library left
+// pending on this thread, so that hip_status() reports only their own.
+void drop_pending_error() { (void)hipGetLastError(); }
+
+cqr_status hip_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CQR_OK : hip_fail(e);
+}
 
 hipEvent_t take_event(cqr_plan_s& p) {
   if (!p.pool.empty()) {
@@ -264,19 +280,64 @@ void prof_clear(cqr_plan_s& p) {
   p.recs.clear();
 }
 
-// Typed wrappers: flops and minimum bytes of each product.
+// Typed wrappers: flops and minimum bytes of each launch.  A split product
+// is recorded as two launches: the product (its phase) and the reduction of
+// its partial tiles (PH_REDUCE).
+int tag_of(int phase) {
+  if (phase == PH_TRAIL_TN || phase == PH_TRAIL_NN) return cqr::TAG_TRAIL;
+  if (phase == PH_REPROJ_TN || phase == PH_REPROJ_NN) return cqr::TAG_REPROJ;
+  return cqr::TAG_PANEL;
+}
+
+double partial_bytes(int nsplit, int ntiles) { return 8.0 * nsplit * ntiles * cqr::kTile * cqr::kTile; }
+
 void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N,
         int64_t K, double* C, int64_t ldc, double* C2, int64_t ldc2, const cqr::Scratch& s, hipStream_t st) {
-  double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N + (double)M * N);
-  prof(p, phase, fl, by, st, [&] { cqr::launch_tn(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s, st); });
+  if (M <= 0 || N <= 0) return;
+  const cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s);
+  const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N);
+  const double out = 8.0 * (double)M * N * (C2 ? 3.0 : 1.0);
+  const int tag = tag_of(phase);
+  if (a.nsplit > 1) {
+    prof(p, phase, fl, by + partial_bytes(a.nsplit, a.ntiles), st, [&] { cqr::launch_tn_product(a, tag, st); });
+    prof(p, PH_REDUCE, (a.nsplit - 1.0) * M * N, partial_bytes(a.nsplit, a.ntiles) + out, st,
+         [&] { cqr::launch_tn_reduce(a, st); });
+  } else {
+    prof(p, phase, fl, by + out, st, [&] { cqr::launch_tn_product(a, tag, st); });
+  }
 }
 
 void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64_t lda, const double* B,
         int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st) {
-  double fl = 2.0 * M * N * (double)K, by = 8.0 * (2.0 * M * N + (double)M * K + (double)K * N);
-  prof(p, phase, fl, by, st, [&] { cqr::launch_nn_sub(C, ldc, A, lda, B, ldb, M, N, K, s, st); });
+  if (M <= 0 || N <= 0 || K <= 0) return;
+  const cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s);
+  const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)M * K + (double)K * N);
+  const double upd = 16.0 * (double)M * N;
+  const int tag = tag_of(phase);
+  if (a.nsplit > 1) {
+    prof(p, phase, fl, by + partial_bytes(a.nsplit, a.ntiles), st, [&] { cqr::launch_nn_product(a, tag, st); });
+    prof(p, PH_REDUCE, (double)a.nsplit * M * N, partial_bytes(a.nsplit, a.ntiles) + upd, st,
+         [&] { cqr::launch_nn_reduce(a, st); });
+  } else {
+    prof(p, phase, fl, by + upd, st, [&] { cqr::launch_nn_product(a, tag, st); });
+  }
 }
 
+// One Cholesky-QR pass on the panel P (m' x w): Gram product (+ reduction),
+// Cholesky factor and inverse, then P <- P R^{-1}.
+void cholqr_pass(cqr_plan_s& p, double* P, int64_t ldq, int w, int pass, double* Rout, int64_t ldr, int panel,
+                 const cqr::Scratch& s, hipStream_t st) {
+  const int64_t mp = p.mp;
+  const cqr::TnArgs g = cqr::gram_setup(P, ldq, mp, w, s);
+  const double gfl = 2.0 * mp * w * w, gby = 8.0 * mp * w;
+  prof(p, PH_GRAM, gfl, gby + partial_bytes(g.nsplit, 1), st, [&] { cqr::launch_tn_product(g, cqr::TAG_PANEL, st); });
+  if (g.nsplit > 1)
+    prof(p, PH_REDUCE, (g.nsplit - 1.0) * w * w, partial_bytes(g.nsplit, 1) + 8.0 * w * w, st,
+         [&] { cqr::launch_gram_sum(g, s, st); });
+  prof(p, PH_CHOL, 2.0 * w * w * w, 8.0 * w * w * (pass == 1 ? 3.0 : 4.0), st,
+       [&] { cqr::launch_chol(w, pass, Rout, ldr, panel, s, st); });
+  prof(p, PH_APPLY, gfl, 2 * gby, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
+}
 
 // Panel of w columns starting at column c: leaves of <= kLeaf columns are
 // orthogonalised by two Cholesky-QR passes; wider panels are split, the right
@@ -286,12 +347,8 @@ void factor_panel(cqr_plan_s& p, double* Q, int64_t ldq, double* R, int64_t ldr,
   const int64_t mp = p.mp;
   if (w <= kLeaf) {
     double* P = Q + c * ldq;
-    const double gfl = 2.0 * mp * w * w, gby = 8.0 * mp * w;
-    prof(p, PH_GRAM, gfl, gby, st, [&] { cqr::launch_gram_chol(P, ldq, mp, w, 1, nullptr, 0, panel, s, st); });
-    prof(p, PH_APPLY, gfl, 2 * gby, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
-    prof(p, PH_GRAM, gfl, gby, st,
-         [&] { cqr::launch_gram_chol(P, ldq, mp, w, 2, R + c + c * ldr, ldr, panel, s, st); });
-    prof(p, PH_APPLY, gfl, 2 * gby, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
+    cholqr_pass(p, P, ldq, w, 1, nullptr, 0, panel, s, st);
+    cholqr_pass(p, P, ldq, w, 2, R + c + c * ldr, ldr, panel, s, st);
     return;
   }
   int h = (w / 2 + 15) / 16 * 16;
@@ -308,6 +365,8 @@ void factor_panel(cqr_plan_s& p, double* Q, int64_t ldq, double* R, int64_t ldr,
 }  // namespace
 
 extern "C" {
+
+const char* coded_qr_hip_error_name(void) { return hipGetErrorName(t_hip_error); }
 
 const char* coded_qr_status_string(cqr_status s) {
   switch (s) {
@@ -413,10 +472,12 @@ cqr_status coded_qr_profile_read(cqr_plan p, int32_t phase, double* total_ms, in
   int64_t cnt = 0;
   for (auto& r : p->recs) {
     if (r.phase != phase) continue;
-    if (!r.a || !r.b) return CQR_EHIP;
-    if (hipEventSynchronize(r.b) != hipSuccess) return CQR_EHIP;
+    if (!r.a || !r.b) return hip_fail(hipErrorInvalidResourceHandle);
+    hipError_t he = hipEventSynchronize(r.b);
+    if (he != hipSuccess) return hip_fail(he);
     float e = 0.f;
-    if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return CQR_EHIP;
+    he = hipEventElapsedTime(&e, r.a, r.b);
+    if (he != hipSuccess) return hip_fail(he);
     ms += e;
     fl += r.flops;
     by += r.bytes;
@@ -441,6 +502,7 @@ int32_t coded_qr_plan_ftol(cqr_plan p) { return p ? p->ftol : -1; }
 size_t coded_qr_workspace_bytes(cqr_plan p) { return p ? p->ws_bytes : 0; }
 
 cqr_status coded_qr_encode(cqr_plan p, double* At, int64_t ldat, hipStream_t st) {
+  drop_pending_error();
   if (!p || !At || ldat < p->mp) return CQR_EINVAL;
   if (p->cfg.kv == 0 && p->cfg.kh == 0) return CQR_OK;
   cqr::EncodeArgs a{};
@@ -465,6 +527,7 @@ cqr_status coded_qr_encode(cqr_plan p, double* At, int64_t ldat, hipStream_t st)
 
 cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, int32_t pb, int32_t pe,
                            void* ws, size_t ws_bytes, hipStream_t st) {
+  drop_pending_error();
   if (!p || !Q || !R || !ws) return CQR_EINVAL;
   const int64_t n = p->cfg.n, b = p->cfg.b, N = p->N, mp = p->mp;
   const int npan = (int)(n / b);
@@ -479,8 +542,9 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
   const bool la = p->cfg.lookahead && pe - pb > 1 && side_ready(*p);
   if (la) {
     // the side stream starts after everything already queued on `st`
-    if (hipEventRecord(p->ev_main, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_main, 0) != hipSuccess)
-      return CQR_EHIP;
+    hipError_t e = hipEventRecord(p->ev_main, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_main, 0);
+    if (e != hipSuccess) return hip_fail(e);
   }
   // Panel k's update of columns [from, N):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
   auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
@@ -501,35 +565,46 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
     if (c1 >= N) continue;
     // columns right of panel k carry panel k-1's update from the side stream
-    if (side_pending && hipStreamWaitEvent(st, p->ev_side, 0) != hipSuccess) return CQR_EHIP;
+    if (side_pending) {
+      const hipError_t e = hipStreamWaitEvent(st, p->ev_side, 0);
+      if (e != hipSuccess) return hip_fail(e);
+    }
     side_pending = false;
     if (la && k + 1 < pe && c1 + b < N) {
       // lookahead: the next panel's columns now, the rest on the side stream
       trail(c0, c1, c1 + b, s, st);
-      if (hipEventRecord(p->ev_main, st) != hipSuccess || hipStreamWaitEvent(p->side, p->ev_main, 0) != hipSuccess)
-        return CQR_EHIP;
+      hipError_t e = hipEventRecord(p->ev_main, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_main, 0);
+      if (e != hipSuccess) return hip_fail(e);
       trail(c0, c1 + b, N, s2, p->side);
-      if (hipEventRecord(p->ev_side, p->side) != hipSuccess) return CQR_EHIP;
+      e = hipEventRecord(p->ev_side, p->side);
+      if (e != hipSuccess) return hip_fail(e);
       side_pending = true;
     } else {
       trail(c0, c1, N, s, st);
     }
   }
-  if (side_pending && hipStreamWaitEvent(st, p->ev_side, 0) != hipSuccess) return CQR_EHIP;
+  if (side_pending) {
+    const hipError_t e = hipStreamWaitEvent(st, p->ev_side, 0);
+    if (e != hipSuccess) return hip_fail(e);
+  }
   return hip_status();
 }
 
 cqr_status coded_qr_ws_info(cqr_plan p, const void* ws, hipStream_t st, int32_t* info) {
   if (!p || !ws || !info) return CQR_EINVAL;
-  if (hipStreamSynchronize(st) != hipSuccess) return CQR_EHIP;
+  hipError_t he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
   int32_t v = 0;
-  if (hipMemcpy(&v, ws, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return CQR_EHIP;
+  he = hipMemcpy(&v, ws, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return hip_fail(he);
   *info = v;
   return v ? CQR_EBREAKDOWN : CQR_OK;
 }
 
 cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,
                           int32_t nf, hipStream_t st) {
+  drop_pending_error();
   if (!p || !Q || !R || ldq < p->mp || ldr < p->cfg.n) return CQR_EINVAL;
   cqr_status cs = check_nodes(*p, ij, nf);
   if (cs != CQR_OK) return cs;
@@ -559,6 +634,7 @@ cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t
 
 cqr_status coded_qr_recover(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,
                             int32_t nf, hipStream_t st) {
+  drop_pending_error();
   if (!p || !Q || !R || ldq < p->mp || ldr < p->cfg.n) return CQR_EINVAL;
   cqr_status cs = check_nodes(*p, ij, nf);
   if (cs != CQR_OK) return cs;
@@ -637,6 +713,7 @@ cqr_status coded_qr_recover(cqr_plan p, double* Q, int64_t ldq, double* R, int64
 cqr_status coded_qr_postorth(cqr_plan p, const double* Q, int64_t ldq, double* Qpost, int64_t ldqp,
                              const double* B, int64_t ldb, double* Bpost, int64_t ldbp, int32_t nrhs,
                              hipStream_t st) {
+  drop_pending_error();
   if (!p || !Q || !Qpost || p->cfg.kv == 0 || nrhs < 0) return CQR_EINVAL;
   const int64_t m = p->cfg.m;
   if (ldq < m || ldqp < m) return CQR_EINVAL;

@@ -23,6 +23,7 @@
 namespace cqr {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ v4d mfma(double x, double y, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
@@ -51,6 +52,9 @@ __device__ __forceinline__ void sum_partials(const double* part, int nsplit, int
 #pragma unroll
       for (int q = 0; q < 16; ++q) t[u][q] = p[q * 64 + lane];
     }
+    // keep the 64 loads ahead of the additions (the scheduler would
+    // otherwise pair each load with its add and wait on it)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -70,18 +74,35 @@ __device__ __forceinline__ void sum_partials(const double* part, int nsplit, int
 // instruction covers 4 columns x 256 contiguous bytes.  Requires 16-byte
 // aligned operands with even leading dimensions (else tn_direct_kernel).
 // --------------------------------------------------------------------------
-struct TnArgs {
-  const double* A; int64_t lda;
-  const double* B; int64_t ldb;
-  int M, N; int64_t K;
-  int64_t kchunk; int nsplit; int tilesN; int ntiles;
-  double* C; int64_t ldc;
-  double* C2; int64_t ldc2;
-  double* part;
-};
 
 constexpr int KC = 32;           // k-values per LDS slab
 constexpr int LDP = KC + 2;      // padded LDS column (doubles)
+
+// Store a wave's 32 x 32 quadrant (16 values per lane, element (x, y, r) at
+// row i0 + 16x + li, column j0 + 16y + 4r + g) to C, and add it into C2 if
+// given; the C2 loads are all issued before any store.
+__device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C2, int64_t ldc2, int M, int N,
+                                               int i0, int j0, int li, int g, const double (&v)[16]) {
+  double old[16];
+  if (C2) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
+      const int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
+      old[e] = (i < M && j < N) ? C2[i + (int64_t)j * ldc2] : 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
+    const int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
+    if (i < M && j < N) {
+      C[i + (int64_t)j * ldc] = v[e];
+      if (C2) C2[i + (int64_t)j * ldc2] = old[e] + v[e];
+    }
+  }
+}
 
 __device__ __forceinline__ void tn_store(const TnArgs& a, const v4d (&acc)[2][2], int tile, int split, int wave,
                                          int lane, int i0, int j0) {
@@ -96,22 +117,14 @@ __device__ __forceinline__ void tn_store(const TnArgs& a, const v4d (&acc)[2][2]
         for (int r = 0; r < 4; ++r) mine[((x * 2 + y) * 4 + r) * 64 + lane] = acc[x][y][r];
     return;
   }
+  double v[16];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
-        if (i < a.M && j < a.N) {
-          double v = acc[x][y][r];
-          a.C[i + (int64_t)j * a.ldc] = v;
-          if (a.C2) a.C2[i + (int64_t)j * a.ldc2] += v;
-        }
-      }
+  for (int e = 0; e < 16; ++e) v[e] = acc[e >> 3][(e >> 2) & 1][e & 3];
+  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.N, i0, j0, li, g, v);
 }
 
-__global__ __launch_bounds__(256) void tn_lds_kernel(TnArgs a) {
+template <int TAG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void tn_lds_kernel(TnArgs a) {
   __shared__ double sA[2][64 * LDP];
   __shared__ double sB[2][64 * LDP];
   const int tile = blockIdx.x, split = blockIdx.y;
@@ -119,7 +132,7 @@ __global__ __launch_bounds__(256) void tn_lds_kernel(TnArgs a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
   const int64_t kb = (int64_t)split * a.kchunk;
   const int64_t ke = std::min<int64_t>(a.K, kb + a.kchunk);
-  // staging: thread loads one double2 (k pair lq) of columns lc + 16r, r < 4
+  // staging: thread loads one v2d (k pair lq) of columns lc + 16r, r < 4
   const int lc = tid >> 4, lq = tid & 15;
   const double* ga[4];
   const double* gb[4];
@@ -137,7 +150,6 @@ __global__ __launch_bounds__(256) void tn_lds_kernel(TnArgs a) {
     for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0, 0, 0, 0};
   const int ia0 = (wave & 1) * 32, jb0 = (wave >> 1) * 32;
   const int nfull = (int)((ke - kb) / KC);
-  double2 ra[4], rb[4];
 
   auto compute = [&](int buf) {
 #pragma unroll
@@ -147,8 +159,8 @@ __global__ __launch_bounds__(256) void tn_lds_kernel(TnArgs a) {
       for (int t = 0; t < 2; ++t) {
         const double* pa = &sA[buf][(ia0 + 16 * t + li) * LDP + kk + 4 * g];
         const double* pb = &sB[buf][(jb0 + 16 * t + li) * LDP + kk + 4 * g];
-        double2 a0 = *reinterpret_cast<const double2*>(pa), a1 = *reinterpret_cast<const double2*>(pa + 2);
-        double2 b0 = *reinterpret_cast<const double2*>(pb), b1 = *reinterpret_cast<const double2*>(pb + 2);
+        v2d a0 = *reinterpret_cast<const v2d*>(pa), a1 = *reinterpret_cast<const v2d*>(pa + 2);
+        v2d b0 = *reinterpret_cast<const v2d*>(pb), b1 = *reinterpret_cast<const v2d*>(pb + 2);
         xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
         xb[t][0] = b0.x; xb[t][1] = b0.y; xb[t][2] = b1.x; xb[t][3] = b1.y;
       }
@@ -160,37 +172,57 @@ __global__ __launch_bounds__(256) void tn_lds_kernel(TnArgs a) {
           for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
     }
   };
+  // slab sl's first k (clamped to the last full slab: prefetches past the end
+  // reload cached data that is never used)
+  auto koff = [&](int sl) { return kb + (int64_t)std::min(sl, nfull - 1) * KC; };
 
   if (nfull > 0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      ra[r] = *reinterpret_cast<const double2*>(ga[r] + kb);
-      rb[r] = *reinterpret_cast<const double2*>(gb[r] + kb);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      *reinterpret_cast<double2*>(&sA[0][(lc + 16 * r) * LDP + 2 * lq]) = ra[r];
-      *reinterpret_cast<double2*>(&sB[0][(lc + 16 * r) * LDP + 2 * lq]) = rb[r];
-    }
+    // three-stage pipeline: slab sl in LDS is multiplied while the register
+    // set of slab sl+1 (issued one slab earlier) lands and slab sl+2 is
+    // requested into the other set; the two sets alternate explicitly
+    v2d ra0[4], rb0[4], ra1[4], rb1[4];
+#define CQR_TN_LOAD(RA, RB, K) {                                        \
+    RA[0] = *reinterpret_cast<const v2d*>(ga[0] + (K));              \
+    RB[0] = *reinterpret_cast<const v2d*>(gb[0] + (K));              \
+    RA[1] = *reinterpret_cast<const v2d*>(ga[1] + (K));              \
+    RB[1] = *reinterpret_cast<const v2d*>(gb[1] + (K));              \
+    RA[2] = *reinterpret_cast<const v2d*>(ga[2] + (K));              \
+    RB[2] = *reinterpret_cast<const v2d*>(gb[2] + (K));              \
+    RA[3] = *reinterpret_cast<const v2d*>(ga[3] + (K));              \
+    RB[3] = *reinterpret_cast<const v2d*>(gb[3] + (K));              \
+  }
+#define CQR_TN_PUT(BUF, RA, RB) {                                       \
+    *reinterpret_cast<v2d*>(&sA[BUF][(lc + 0) * LDP + 2 * lq]) = RA[0];      \
+    *reinterpret_cast<v2d*>(&sB[BUF][(lc + 0) * LDP + 2 * lq]) = RB[0];      \
+    *reinterpret_cast<v2d*>(&sA[BUF][(lc + 16) * LDP + 2 * lq]) = RA[1];      \
+    *reinterpret_cast<v2d*>(&sB[BUF][(lc + 16) * LDP + 2 * lq]) = RB[1];      \
+    *reinterpret_cast<v2d*>(&sA[BUF][(lc + 32) * LDP + 2 * lq]) = RA[2];      \
+    *reinterpret_cast<v2d*>(&sB[BUF][(lc + 32) * LDP + 2 * lq]) = RB[2];      \
+    *reinterpret_cast<v2d*>(&sA[BUF][(lc + 48) * LDP + 2 * lq]) = RA[3];      \
+    *reinterpret_cast<v2d*>(&sB[BUF][(lc + 48) * LDP + 2 * lq]) = RB[3];      \
+  }
+    CQR_TN_LOAD(ra0, rb0, koff(0))
+    CQR_TN_LOAD(ra1, rb1, koff(1))
+    CQR_TN_PUT(0, ra0, rb0)
     __syncthreads();
-    for (int sl = 0; sl < nfull; ++sl) {
-      const int buf = sl & 1;
-      // prefetch the next slab into registers (clamped: the last iteration
-      // reloads the current slab, which is cached and not used)
-      const int64_t kn = kb + (int64_t)((sl + 1 < nfull) ? sl + 1 : sl) * KC;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        ra[r] = *reinterpret_cast<const double2*>(ga[r] + kn);
-        rb[r] = *reinterpret_cast<const double2*>(gb[r] + kn);
-      }
-      compute(buf);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        *reinterpret_cast<double2*>(&sA[buf ^ 1][(lc + 16 * r) * LDP + 2 * lq]) = ra[r];
-        *reinterpret_cast<double2*>(&sB[buf ^ 1][(lc + 16 * r) * LDP + 2 * lq]) = rb[r];
-      }
+    int sl = 0;
+    for (; sl + 2 <= nfull; sl += 2) {
+      CQR_TN_LOAD(ra0, rb0, koff(sl + 2))
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      CQR_TN_PUT(1, ra1, rb1)
+      __syncthreads();
+      CQR_TN_LOAD(ra1, rb1, koff(sl + 3))
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+      CQR_TN_PUT(0, ra0, rb0)
       __syncthreads();
     }
+    if (sl < nfull) compute(0);
+#undef CQR_TN_LOAD
+#undef CQR_TN_PUT
   }
   const int64_t kt = kb + (int64_t)nfull * KC;
   if (kt < ke) {
@@ -201,13 +233,13 @@ __global__ __launch_bounds__(256) void tn_lds_kernel(TnArgs a) {
       const int64_t k = kt + 2 * lq;
       const double* pa = ga[r] - 2 * lq;
       const double* pb = gb[r] - 2 * lq;
-      double2 va, vb;
+      v2d va, vb;
       va.x = (k < ke) ? pa[k] : 0.0;
       va.y = (k + 1 < ke) ? pa[k + 1] : 0.0;
       vb.x = (k < ke) ? pb[k] : 0.0;
       vb.y = (k + 1 < ke) ? pb[k + 1] : 0.0;
-      *reinterpret_cast<double2*>(&sA[buf][(lc + 16 * r) * LDP + 2 * lq]) = va;
-      *reinterpret_cast<double2*>(&sB[buf][(lc + 16 * r) * LDP + 2 * lq]) = vb;
+      *reinterpret_cast<v2d*>(&sA[buf][(lc + 16 * r) * LDP + 2 * lq]) = va;
+      *reinterpret_cast<v2d*>(&sB[buf][(lc + 16 * r) * LDP + 2 * lq]) = vb;
     }
     __syncthreads();
     compute(buf);
@@ -270,19 +302,7 @@ __global__ __launch_bounds__(256) void tn_reduce_kernel(TnArgs a) {
   const int i0 = tm * 64 + (wave & 1) * 32, j0 = tn * 64 + (wave >> 1) * 32;
   double v[16];
   sum_partials(a.part, a.nsplit, a.ntiles, tile, wave, lane, v);
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
-        if (i < a.M && j < a.N) {
-          double val = v[(x * 2 + y) * 4 + r];
-          a.C[i + (int64_t)j * a.ldc] = val;
-          if (a.C2) a.C2[i + (int64_t)j * a.ldc2] += val;
-        }
-      }
+  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.N, i0, j0, li, g, v);
 }
 
 static bool aligned16(const void* p, int64_t ld) {
@@ -290,18 +310,19 @@ static bool aligned16(const void* p, int64_t ld) {
 }
 
 static int pick_split(int tiles, int64_t K, int64_t cap) {
-  // ~768 blocks in flight; each split keeps at least 512 rows of the reduction
-  int want = std::max(1, 768 / std::max(1, tiles));
-  int64_t maxs = std::max<int64_t>(1, K / 512);
+  // ~512 blocks (two per CU); each split keeps at least 256 rows (8 slabs)
+  int want = std::max(1, (512 + tiles - 1) / std::max(1, tiles));
+  int64_t maxs = std::max<int64_t>(1, K / 256);
   int ns = (int)std::min<int64_t>(want, maxs);
   while (ns > 1 && (int64_t)ns * tiles > cap) --ns;
   return ns;
 }
 
-// Launch the split-K product; returns the number of splits (partials left in
-// s.part when > 1).  With reduce_here the tiles are summed into C right away.
-static int tn_partials(TnArgs& a, int M, int N, int64_t K, const Scratch& s, hipStream_t st, bool reduce_here,
-                       int force_split = 0) {
+TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
+                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split) {
+  TnArgs a{};
+  a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
+  a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2;
   const int tilesM = (M + kTile - 1) / kTile, tilesN = (N + kTile - 1) / kTile;
   const int tiles = tilesM * tilesN;
   int ns = force_split > 0 ? force_split : pick_split(tiles, K, s.npart);
@@ -311,22 +332,27 @@ static int tn_partials(TnArgs& a, int M, int N, int64_t K, const Scratch& s, hip
   ns = (int)((K + kchunk - 1) / kchunk);
   a.M = M; a.N = N; a.K = K; a.kchunk = kchunk; a.nsplit = ns; a.tilesN = tilesN; a.ntiles = tiles;
   a.part = s.part;
-  const bool vec = aligned16(a.A, a.lda) && aligned16(a.B, a.ldb);
-  if (vec)
-    hipLaunchKernelGGL(tn_lds_kernel, dim3(tiles, ns), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(tn_direct_kernel, dim3(tiles, ns), dim3(256), 0, st, a);
-  if (ns > 1 && reduce_here) hipLaunchKernelGGL(tn_reduce_kernel, dim3(tiles), dim3(256), 0, st, a);
-  return ns;
+  a.vec = aligned16(A, lda) && aligned16(B, ldb);
+  return a;
 }
 
-void launch_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K,
-               double* C, int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, hipStream_t st) {
-  if (M <= 0 || N <= 0) return;
-  TnArgs a{};
-  a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
-  a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2;
-  tn_partials(a, M, N, K, s, st, true);
+void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return;
+  const dim3 grid(a.ntiles, a.nsplit);
+  if (!a.vec) {
+    hipLaunchKernelGGL(tn_direct_kernel, grid, dim3(256), 0, st, a);
+    return;
+  }
+  switch (tag) {
+    case TAG_TRAIL: hipLaunchKernelGGL(tn_lds_kernel<TAG_TRAIL>, grid, dim3(256), 0, st, a); break;
+    case TAG_REPROJ: hipLaunchKernelGGL(tn_lds_kernel<TAG_REPROJ>, grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL(tn_lds_kernel<TAG_PANEL>, grid, dim3(256), 0, st, a); break;
+  }
+}
+
+void launch_tn_reduce(const TnArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0 || a.nsplit <= 1) return;
+  hipLaunchKernelGGL(tn_reduce_kernel, dim3(a.ntiles), dim3(256), 0, st, a);
 }
 
 // --------------------------------------------------------------------------
@@ -368,134 +394,208 @@ __global__ __launch_bounds__(256) void gram_sum_kernel(CholArgs a) {
   if (i < a.w && j < a.w) a.W[i + j * a.w] = v;
 }
 
-// Exact path: upper Cholesky factor R of W (64 x 64, identity-padded in Rl)
-// by four wavefronts.  Thread (tx, ty) holds column tx, rows ty + 4q (q < 16)
-// in registers; row j of R is exchanged through LDS buffers alternating with
-// the step parity (two block barriers per step).  Entries below the diagonal
-// are updated too but never read.  On exit Rl holds R (zero below).
-__device__ __forceinline__ void chol4(int tid, double (*rowP)[kLeaf], double (*rowR)[kLeaf], double (*Rl)[kLeaf + 1],
-                                      bool& bad) {
+// 1/sqrt(x) to full double precision: hardware estimate plus one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  const double r = fma(-h, y, 0.5);
+  return fma(y, r, y);
+}
+
+// Exact path.  Gauss elimination of the augmented matrix [W | I] with row j
+// scaled by 1/sqrt(pivot) when it becomes final: since W = R^T R, the same
+// row operations turn W into R and I into R^{-T}, so the Cholesky factor and
+// its inverse come out of one sweep of 64 steps.  Thread (tx, ty) holds
+// column tx of its rows of both halves in 16 register slots; the 64 steps
+// run as 16 groups of 4, pivot row 4G + t being slot 0 of threads ty = t,
+// and after each group the slots shift down by one (slot q then holds row
+// ty + 4(q + G)), so every register index is a compile-time constant.  The
+// current pivot row is published through LDS buffers alternating with the
+// step parity (one block barrier per step); each final row of R goes to Rl
+// and of R^{-T} (transposed, i.e. T = R^{-1}) to Tl.
+__device__ __forceinline__ void chol_aug(int tid, double (*rowW)[kLeaf], double (*rowZ)[kLeaf],
+                                         double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1], bool& bad) {
   const int tx = tid & 63, ty = tid >> 6;
-  double c[16];
+  double c[16], d[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) c[q] = Rl[ty + 4 * q][tx];
+  for (int q = 0; q < 16; ++q) {
+    const int i = ty + 4 * q;
+    c[q] = (i <= tx) ? Rl[i][tx] : Rl[tx][i];    // upper triangle of W, symmetrically
+    d[q] = (i == tx) ? 1.0 : 0.0;
+  }
+  if (ty == 0) {
+    rowW[0][tx] = c[0];
+    rowZ[0][tx] = d[0];
+  }
+#pragma unroll 1
+  for (int G = 0; G < 16; ++G) {
 #pragma unroll
-  for (int j = 0; j < kLeaf; ++j) {
-    const int jq = j >> 2, jt = j & 3, par = j & 1;
-    if (ty == jt) rowP[par][tx] = c[jq];
-    __syncthreads();
-    double piv = rowP[par][j];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      bad = true;
-      piv = 1.0;
+    for (int t = 0; t < 4; ++t) {
+      const int j = 4 * G + t, par = t & 1;
+      __syncthreads();
+      double piv = rowW[par][j];
+      const double wx = rowW[par][tx], zx = rowZ[par][tx];
+      double wi[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) wi[q] = rowW[par][(ty + 4 * (q + G)) & 63];   // wrapped rows: unused slots
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        bad = true;
+        piv = 1.0;
+      }
+      const double inv = rsqrt_nr(piv);
+      const double inv2 = inv * inv;
+      const double fw = wx * inv2, fz = zx * inv2;
+      // the slot holding the next pivot row first, so its owner publishes early
+      const int sn = (t < 3) ? 0 : 1;
+      const bool below = (t < 3) ? (ty > t) : true;   // slot sn holds a row below j
+      c[sn] -= wi[sn] * (below ? fw : 0.0);
+      d[sn] -= wi[sn] * (below ? fz : 0.0);
+      if (ty == ((t + 1) & 3) && j + 1 < kLeaf) {
+        rowW[par ^ 1][tx] = c[sn];
+        rowZ[par ^ 1][tx] = d[sn];
+      }
+      if (ty == t) {
+        Rl[j][tx] = (tx > j) ? wx * inv : (tx == j ? piv * inv : 0.0);
+        Tl[tx][j] = zx * inv;
+      }
+#pragma unroll
+      for (int q = sn + 1; q < 16; ++q) {
+        c[q] -= wi[q] * fw;
+        d[q] -= wi[q] * fz;
+      }
     }
-    const double rjj = sqrt(piv);
-    const double inv = 1.0 / rjj;
-    const double rk = (tx > j) ? rowP[par][tx] * inv : (tx == j ? rjj : 0.0);   // R[j][tx]
-    if (ty == jt) {
-      c[jq] = rk;
-      rowR[par][tx] = rk;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (ty + 4 * q > j) c[q] -= rowR[par][ty + 4 * q] * rk;
+    for (int q = 0; q < 15; ++q) {
+      c[q] = c[q + 1];
+      d[q] = d[q + 1];
+    }
+    c[15] = 0.0;
+    d[15] = 0.0;
   }
   __syncthreads();
+}
+
+// C = A B for 64 x 64 LDS matrices (row-major, padded), upper triangular A
+// and B; wave v computes rows 16v..16v+15 and stores C[i][j] (i, j < w) into
+// the column-major global matrix out (ld ldo).
+__device__ __forceinline__ void tri_mm_store(int tid, const double (*Al)[kLeaf + 1], const double (*Bl)[kLeaf + 1],
+                                             int w, double* out, int64_t ldo) {
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  v4d acc[4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) Rl[ty + 4 * q][tx] = (ty + 4 * q <= tx) ? c[q] : 0.0;
+  for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
+  // C[i][j] needs k in [i, j]: skip k blocks left of the row block
+  for (int k0 = 16 * wave; k0 < kLeaf; k0 += 16) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      const double xa = Al[16 * wave + li][k];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[y] = mfma(Bl[k][16 * y + li], xa, acc[y]);
+    }
+  }
+  const int i = 16 * wave + li;
+#pragma unroll
+  for (int y = 0; y < 4; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * y + 4 * r + g;
+      if (i < w && j < w) out[i + (int64_t)j * ldo] = acc[y][r];
+    }
 }
 
 __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   __shared__ double Rl[kLeaf][kLeaf + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
-  __shared__ double rowP[2][kLeaf];
-  __shared__ double rowR[2][kLeaf];
+  __shared__ double rowW[2][kLeaf];
+  __shared__ double rowZ[2][kLeaf];
   __shared__ int s_exact, s_bad;
-  const int tid = threadIdx.x, wave = tid >> 6, w = a.w;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, w = a.w;
   if (tid == 0) { s_exact = (a.pass == 1); s_bad = 0; }
-  __syncthreads();
-  // W, identity-padded, into LDS; the second pass checks W = I + E, |E| small
-  for (int e = tid; e < kLeaf * kLeaf; e += 256) {
-    const int i = e % kLeaf, k = e / kLeaf;
-    const double val = (i < w && k < w) ? a.W[i + k * w] : (i == k ? 1.0 : 0.0);
-    Rl[i][k] = val;
-    if (a.pass == 2 && !(fabs(val - (i == k ? 1.0 : 0.0)) <= 1e-8)) s_exact = 1;
+  // W (w x w, column-major) into Rl, identity-padded: all loads issued first
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = ty + 4 * q;   // column
+      v[q] = (tx < w && k < w) ? a.W[tx + (int64_t)k * w] : (tx == k ? 1.0 : 0.0);
+    }
+    bool far = false;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = ty + 4 * q;
+      Rl[tx][k] = v[q];
+      far |= !(fabs(v[q] - (tx == k ? 1.0 : 0.0)) <= 1e-8);
+    }
+    __syncthreads();
+    if (a.pass == 2 && far) s_exact = 1;
   }
   __syncthreads();
   if (s_exact) {
     bool bad = false;
-    chol4(tid, rowP, rowR, Rl, bad);
-    if (bad && tid == 0) s_bad = 1;
-    __syncthreads();
-    // T = R^{-1}: wave 0, lane t solves column t by back substitution
-    if (wave == 0) {
-      const int t = tid;
-      double tc[kLeaf];
-#pragma unroll
-      for (int i = kLeaf - 1; i >= 0; --i) {
-        double acc = (t == i) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = i + 1; k < kLeaf; ++k) acc -= Rl[i][k] * tc[k];
-        tc[i] = acc / Rl[i][i];
-      }
-#pragma unroll
-      for (int i = 0; i < kLeaf; ++i) Tl[i][t] = tc[i];
-    }
+    chol_aug(tid, rowW, rowZ, Rl, Tl, bad);
+    if (bad) s_bad = 1;
   } else {
-    // W = I + E, |E| <= 1e-8:  R = I + F with F the strict upper part of E
-    // plus half its diagonal; R^{-1} = I - F up to O(|E|^2), below rounding.
-    for (int e = tid; e < kLeaf * kLeaf; e += 256) {
-      const int i = e % kLeaf, k = e / kLeaf;
-      const double f = (i < k) ? Rl[i][k] : (i == k ? 0.5 * (Rl[i][k] - 1.0) : 0.0);
-      Tl[i][k] = ((i == k) ? 1.0 : 0.0) - f;
+    // W = I + E with |E| <= 1e-8: R = I + F, F = strict upper part of E plus
+    // half its diagonal; R^{-1} = I - F up to O(|E|^2), below rounding.
+    double f[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = ty + 4 * q;
+      f[q] = (i < tx) ? Rl[i][tx] : (i == tx ? 0.5 * (Rl[i][i] - 1.0) : 0.0);
     }
     __syncthreads();
-    for (int e = tid; e < kLeaf * kLeaf; e += 256) {
-      const int i = e % kLeaf, k = e / kLeaf;
-      Rl[i][k] = (i <= k) ? 2.0 * ((i == k) ? 1.0 : 0.0) - Tl[i][k] : 0.0;   // I + F
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = ty + 4 * q;
+      const double id = (i == tx) ? 1.0 : 0.0;
+      Rl[i][tx] = id + f[q];
+      Tl[i][tx] = id - f[q];
     }
   }
   __syncthreads();
-  for (int e = tid; e < w * w; e += 256) a.T[e] = Tl[e % w][e / w];
-  if (a.pass == 1) {
-    for (int e = tid; e < w * w; e += 256) a.R1[e] = Rl[e % w][e / w];
-  } else {
-    // R_panel = R2 R1, R1 staged in LDS (Tl is free once T is stored)
-    __syncthreads();
-    for (int e = tid; e < kLeaf * kLeaf; e += 256) {
-      const int i = e % kLeaf, k = e / kLeaf;
-      Tl[i][k] = (i < w && k < w) ? a.R1[i + k * w] : 0.0;
-    }
-    __syncthreads();
-    const int t = tid & 63, v = tid >> 6;
-    for (int q = 0; q < 16; ++q) {
-      const int i = v + 4 * q;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int p = i & ~3; p < kLeaf; p += 4) {
+  // T (and R1 on the first pass) to global, column-major w x w
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (p + u >= i) acc[u] += Rl[i][p + u] * Tl[p + u][t];
-      }
-      if (i < w && t < w) a.Rout[i + (int64_t)t * a.ldr] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int q = 0; q < 16; ++q) {
+    const int k = ty + 4 * q;
+    if (tx < w && k < w) {
+      a.T[tx + k * w] = Tl[tx][k];
+      if (a.pass == 1) a.R1[tx + k * w] = Rl[tx][k];
     }
+  }
+  if (a.pass == 2) {
+    // R_panel = R2 R1 with R1 staged in Tl (T is stored)
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = ty + 4 * q;
+      Tl[tx][k] = (tx < w && k < w) ? a.R1[tx + k * w] : (tx == k ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    tri_mm_store(tid, Rl, Tl, w, a.Rout, a.ldr);
   }
   if (tid == 0 && s_bad && *a.info == 0) *a.info = 1 + a.panel;
 }
 
-void launch_gram_chol(const double* P, int64_t ldp, int64_t mrows, int w, int pass, double* Rout,
-                      int64_t ldr, int panel, const Scratch& s, hipStream_t st) {
-  TnArgs a{};
-  a.A = P; a.lda = ldp; a.B = P; a.ldb = ldp;
-  a.C = s.W; a.ldc = w; a.C2 = nullptr; a.ldc2 = 0;
+TnArgs gram_setup(const double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s) {
   // one output tile: split the rows finely (>= 128 per block, at most 64 blocks)
-  const int ns = tn_partials(a, w, w, mrows, s, st, false,
-                             (int)std::max<int64_t>(1, std::min<int64_t>(64, mrows / 128)));
+  const int fs = (int)std::max<int64_t>(1, std::min<int64_t>(64, mrows / 128));
+  TnArgs g = tn_setup(P, ldp, P, ldp, w, w, mrows, s.W, w, nullptr, 0, s, fs);
+  return g;
+}
+
+void launch_gram_sum(const TnArgs& g, const Scratch& s, hipStream_t st) {
+  if (g.nsplit <= 1) return;
   CholArgs c{};
-  c.part = s.part; c.nsplit = ns; c.W = s.W;
+  c.part = s.part; c.nsplit = g.nsplit; c.W = s.W; c.w = g.M;
+  hipLaunchKernelGGL(gram_sum_kernel, dim3(16), dim3(256), 0, st, c);
+}
+
+void launch_chol(int w, int pass, double* Rout, int64_t ldr, int panel, const Scratch& s, hipStream_t st) {
+  CholArgs c{};
+  c.part = s.part; c.nsplit = 1; c.W = s.W;
   c.w = w; c.pass = pass; c.panel = panel;
   c.T = s.T; c.R1 = s.R1; c.Rout = Rout; c.ldr = ldr; c.info = s.info;
-  if (ns > 1) hipLaunchKernelGGL(gram_sum_kernel, dim3(16), dim3(256), 0, st, c);
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, c);
 }
 
@@ -507,45 +607,51 @@ void launch_gram_chol(const double* P, int64_t ldp, int64_t mrows, int w, int pa
 __global__ __launch_bounds__(256) void apply_kernel(double* P, int64_t ldp, int64_t mrows, int w,
                                                     const double* T) {
   __shared__ double tileP[kLeaf][64 + 1];   // [col][row]
+  __shared__ double tileT[kLeaf][kLeaf + 1];   // [k][j]
   const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * w; e += 256) {
-    const int rr = e % 64, c = e / 64;
-    const int64_t row = r0 + rr;
-    tileP[c][rr] = (row < mrows) ? P[row + (int64_t)c * ldp] : 0.0;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  {
+    // every load of the block in flight at once: 16 of P and 16 of T per thread
+    const int64_t row = r0 + tx;
+    const bool rok = row < mrows;
+    double vp[16], vt[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = ty + 4 * q;
+      vp[q] = (rok && c < w) ? P[row + (int64_t)c * ldp] : 0.0;
+      vt[q] = (tx < w && c < w) ? T[tx + c * w] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = ty + 4 * q;
+      tileP[c][tx] = vp[q];
+      tileT[tx][c] = vt[q];
+    }
   }
   __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int wave = ty, lane = tx, li = lane & 15, g = lane >> 4;
   const int rl = wave * 16 + li;
   v4d acc[4];
 #pragma unroll
   for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
-  for (int k0 = 0; k0 < w; k0 += 16) {
-    double xb[4][4];
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int j = 16 * y + li;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = k0 + 4 * g + s;
-        xb[y][s] = (k < w && j < w) ? T[k + (int64_t)j * w] : 0.0;
-      }
-    }
+#pragma unroll 4
+  for (int k0 = 0; k0 < kLeaf; k0 += 16) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = k0 + 4 * g + s;
-      const double xa = (k < w) ? tileP[k][rl] : 0.0;
+      const double xa = tileP[k][rl];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[y] = mfma(xb[y][s], xa, acc[y]);
+      for (int y = 0; y < 4; ++y) acc[y] = mfma(tileT[k][16 * y + li], xa, acc[y]);
     }
   }
+  const int64_t row = r0 + rl;
+  if (row >= mrows) return;
 #pragma unroll
   for (int y = 0; y < 4; ++y)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = 16 * y + 4 * r + g;
-      const int64_t row = r0 + wave * 16 + li;
-      if (j < w && row < mrows) P[row + (int64_t)j * ldp] = acc[y][r];
+      if (j < w) P[row + (int64_t)j * ldp] = acc[y][r];
     }
 }
 
@@ -557,106 +663,202 @@ void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s
 // --------------------------------------------------------------------------
 // Rank-K update  C -= A B  (A: M x K, B: K x N, C: M x N, column-major).
 // Tile 64 x 64 per block; wave w takes rows 16w..16w+15 and all 64 columns
-// (4 accumulator blocks).  Short K (the trailing update, K = b): C is loaded
-// at the start so its latency overlaps the products.  Long K with few tiles
+// (4 accumulator blocks).  K advances in slabs of 64: the B slab (64 x 64) is
+// staged in LDS and shared by the four waves, each lane keeps its 16 A values
+// of a slab in registers, and the next slab's A and B loads are in flight
+// while the current slab is multiplied (two A register sets alternate
+// explicitly).  Short K (the trailing update, K = b): C is loaded at the start
+// so all of a tile's loads are in flight together.  Long K with few tiles
 // (re-projection): the K range is split over blocks and nn_reduce_kernel
 // subtracts the partial tiles from C in split order.
 // --------------------------------------------------------------------------
-struct NnArgs {
-  double* C; int64_t ldc;
-  const double* A; int64_t lda;
-  const double* B; int64_t ldb;
-  int64_t M; int N; int K;
-  int kchunk; int nsplit; int tilesN; int ntiles; int vec;
-  double* part;
+
+constexpr int NK = 64;   // k per slab of the rank-K update
+
+// Shared pieces of the rank-K update kernels.  B staging: thread t moves
+// B[k0 + 16(t & 3) + e][jb + (t >> 2)], e < 16 (8 vector loads from one
+// column); columns past N read column 0 and feed only unstored outputs.
+struct NnTile {
+  int tm, tn, wave, lane, li, g, tid;
+  int64_t i, ic;
+  int jb;
+  bool aok;
+  const double* ar;   // A[ic][g]: lane (li, g) supplies A[i][k0 + 4m + g] to product m
+  const double* bp;   // B[16(t & 3)][jb + (t >> 2)]
 };
 
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void nn_kernel(NnArgs a) {
-  const int tile = blockIdx.x, split = blockIdx.y;
-  const int tm = tile / a.tilesN, tn = tile % a.tilesN;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
-  const int64_t i = (int64_t)tm * 64 + wave * 16 + li;
-  const int jb = tn * 64;
-  const bool aok = i < a.M;
-  const int64_t ic = aok ? i : 0;                 // clamped row: valid address, result unused
-  const int kb = split * a.kchunk;
-  const int ke = std::min(a.K, kb + a.kchunk);
-  double cval[4][4];
-  if (!SPLIT) {
+__device__ __forceinline__ NnTile nn_tile(const NnArgs& a, int tile) {
+  NnTile t;
+  t.tm = tile / a.tilesN;
+  t.tn = tile % a.tilesN;
+  t.tid = threadIdx.x;
+  t.wave = t.tid >> 6;
+  t.lane = t.tid & 63;
+  t.li = t.lane & 15;
+  t.g = t.lane >> 4;
+  t.i = (int64_t)t.tm * 64 + t.wave * 16 + t.li;
+  t.jb = t.tn * 64;
+  t.aok = t.i < a.M;
+  t.ic = t.aok ? t.i : 0;            // clamped row: valid address, result unused
+  t.ar = a.A + t.ic + (int64_t)t.g * a.lda;
+  const int jc = t.jb + (t.tid >> 2);
+  t.bp = a.B + 16 * (t.tid & 3) + (int64_t)(jc < a.N ? jc : 0) * a.ldb;
+  return t;
+}
+
+__device__ __forceinline__ void nn_load_a(const NnArgs& a, const NnTile& t, int k0, double (&xa)[16]) {
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+  for (int m = 0; m < 16; ++m) xa[m] = t.ar[(int64_t)(k0 + 4 * m) * a.lda];
+}
+
+__device__ __forceinline__ void nn_load_b(const NnTile& t, int k0, v2d (&rb)[8]) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = jb + 16 * y + 4 * r + g;
-        cval[y][r] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
-      }
+  for (int e = 0; e < 8; ++e) rb[e] = *reinterpret_cast<const v2d*>(t.bp + k0 + 2 * e);
+}
+
+__device__ __forceinline__ void nn_put_b(double (*sBb)[64 + 1], const NnTile& t, const v2d (&rb)[8]) {
+  const int kq = 16 * (t.tid & 3), j = t.tid >> 2;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    sBb[kq + 2 * e][j] = rb[e].x;
+    sBb[kq + 2 * e + 1][j] = rb[e].y;
   }
-  const double* ar = a.A + ic;
-  const double* bc[4];
+}
+
+// Partial slab [k0, ke): zero beyond ke on both operands (scalar loads).
+__device__ __forceinline__ void nn_load_tail(const NnArgs& a, const NnTile& t, int k0, int ke, double (&xa)[16],
+                                             double (*sBb)[64 + 1]) {
 #pragma unroll
-  for (int y = 0; y < 4; ++y) {
-    const int j = jb + 16 * y + li;
-    bc[y] = a.B + (int64_t)(j < a.N ? j : 0) * a.ldb;
+  for (int m = 0; m < 16; ++m) {
+    const int k = k0 + 4 * m + t.g;
+    xa[m] = (k < ke) ? t.ar[(int64_t)(k0 + 4 * m) * a.lda] : 0.0;
   }
+  const int kq = 16 * (t.tid & 3), j = t.tid >> 2;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) sBb[kq + e][j] = (k0 + kq + e < ke) ? t.bp[k0 + e] : 0.0;
+}
+
+__device__ __forceinline__ void nn_mma(v4d (&acc)[4], const double (*sBb)[64 + 1], const NnTile& t,
+                                       const double (&xa)[16]) {
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int k = 4 * m + t.g;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[y] = mfma(sBb[k][16 * y + t.li], xa[m], acc[y]);
+  }
+}
+
+// C -= A B for K <= 64 (the trailing update: K = b): every load of the tile
+// (C, A, the B slab) is issued before the first product.
+template <int TAG>
+__global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
+  __shared__ double sB[NK][64 + 1];
+  const NnTile t = nn_tile(a, blockIdx.x);
+  double cval[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = t.jb + 16 * (e >> 2) + 4 * (e & 3) + t.g;
+    cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+  }
+  double xa[16];
+  if (a.K == NK && a.vec) {
+    v2d rb[8];
+    nn_load_a(a, t, 0, xa);
+    nn_load_b(t, 0, rb);
+    __builtin_amdgcn_sched_barrier(0);
+    nn_put_b(sB, t, rb);
+  } else {
+    nn_load_tail(a, t, 0, a.K, xa, sB);
+  }
+  __syncthreads();
   v4d acc[4];
 #pragma unroll
   for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
-  double xa[4], xb[4][4], na[4], nb[4][4];
-  auto load_full = [&](int k0, double (&ya)[4], double (&yb)[4][4]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) ya[s] = ar[(int64_t)(k0 + 4 * g + s) * a.lda];
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const double2* pb = reinterpret_cast<const double2*>(bc[y] + k0 + 4 * g);
-      const double2 b0 = pb[0], b1 = pb[1];
-      yb[y][0] = b0.x; yb[y][1] = b0.y; yb[y][2] = b1.x; yb[y][3] = b1.y;
-    }
-  };
-  auto mma = [&](const double (&ya)[4], const double (&yb)[4][4]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[y] = mfma(yb[y][s], ya[s], acc[y]);
-  };
-  const int kfull = a.vec ? kb + (ke - kb) / 16 * 16 : kb;
-  if (kfull > kb) {
-    load_full(kb, xa, xb);
-    int k0 = kb;
-    for (; k0 + 16 < kfull; k0 += 32) {
-      load_full(k0 + 16, na, nb);
-      mma(xa, xb);
-      load_full((k0 + 32 < kfull) ? k0 + 32 : k0 + 16, xa, xb);
-      mma(na, nb);
-    }
-    if (k0 < kfull) mma(xa, xb);
-  }
-  for (int k0 = kfull; k0 < ke; k0 += 16) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = k0 + 4 * g + s;
-      const bool kok = k < ke;
-      xa[s] = kok ? ar[(int64_t)k * a.lda] : 0.0;
-#pragma unroll
-      for (int y = 0; y < 4; ++y) xb[y][s] = kok ? bc[y][k] : 0.0;
-    }
-    mma(xa, xb);
-  }
-  if (SPLIT) {
-    double* mine = a.part + part_off(split, a.ntiles, tile, wave);
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) mine[(y * 4 + r) * 64 + lane] = acc[y][r];
-    return;
-  }
-  if (!aok) return;
+  nn_mma(acc, sB, t, xa);
+  if (!t.aok) return;
 #pragma unroll
   for (int y = 0; y < 4; ++y)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j = jb + 16 * y + 4 * r + g;
-      if (j < a.N) a.C[i + (int64_t)j * a.ldc] = cval[y][r] - acc[y][r];
+      const int j = t.jb + 16 * y + 4 * r + t.g;
+      if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
+    }
+}
+
+// Long K: slabs of 64 with the next slab's A and B loads in flight while the
+// current slab is multiplied (A register sets alternate explicitly).  SPLIT:
+// the block's K range is one split and its partial tile is stored for
+// nn_reduce_kernel; otherwise C is read at the end and updated in place.
+template <bool SPLIT, int TAG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_kernel(NnArgs a) {
+  __shared__ double sB[2][NK][64 + 1];
+  const int split = blockIdx.y;
+  const NnTile t = nn_tile(a, blockIdx.x);
+  const int kb = split * a.kchunk;
+  const int ke = std::min(a.K, kb + a.kchunk);
+  const int nfull = a.vec ? (ke - kb) / NK : 0;
+  v4d acc[4];
+#pragma unroll
+  for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
+  auto koff = [&](int sl) { return kb + std::min(sl, nfull - 1) * NK; };
+  if (nfull > 0) {
+    double xa0[16], xa1[16];
+    v2d rb[8];
+    nn_load_a(a, t, koff(0), xa0);
+    nn_load_b(t, koff(0), rb);
+    __builtin_amdgcn_sched_barrier(0);
+    nn_put_b(sB[0], t, rb);
+    __syncthreads();
+    int sl = 0;
+    for (; sl + 2 <= nfull; sl += 2) {
+      nn_load_a(a, t, koff(sl + 1), xa1);
+      nn_load_b(t, koff(sl + 1), rb);
+      __builtin_amdgcn_sched_barrier(0);
+      nn_mma(acc, sB[0], t, xa0);
+      __builtin_amdgcn_sched_barrier(0);
+      nn_put_b(sB[1], t, rb);
+      __syncthreads();
+      nn_load_a(a, t, koff(sl + 2), xa0);
+      nn_load_b(t, koff(sl + 2), rb);
+      __builtin_amdgcn_sched_barrier(0);
+      nn_mma(acc, sB[1], t, xa1);
+      __builtin_amdgcn_sched_barrier(0);
+      nn_put_b(sB[0], t, rb);
+      __syncthreads();
+    }
+    if (sl < nfull) nn_mma(acc, sB[0], t, xa0);
+  }
+  const int kt = kb + nfull * NK;
+  for (int k0 = kt; k0 < ke; k0 += NK) {
+    // partial (or unaligned) slabs; the buffer not read by the last full slab
+    const int buf = ((k0 - kb) / NK) & 1;
+    double xa[16];
+    nn_load_tail(a, t, k0, ke, xa, sB[buf]);
+    __syncthreads();
+    nn_mma(acc, sB[buf], t, xa);
+    __syncthreads();
+  }
+  if (SPLIT) {
+    double* mine = a.part + part_off(split, a.ntiles, blockIdx.x, t.wave);
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mine[(y * 4 + r) * 64 + t.lane] = acc[y][r];
+    return;
+  }
+  double cval[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = t.jb + 16 * (e >> 2) + 4 * (e & 3) + t.g;
+    cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+  }
+  if (!t.aok) return;
+#pragma unroll
+  for (int y = 0; y < 4; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = t.jb + 16 * y + 4 * r + t.g;
+      if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
     }
 }
 
@@ -666,44 +868,70 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int64_t i = (int64_t)tm * 64 + wave * 16 + li;
   const int jb = tn * 64;
+  const bool aok = i < a.M;
+  const int64_t ic = aok ? i : 0;
   double v[16];
   sum_partials(a.part, a.nsplit, a.ntiles, tile, wave, lane, v);
-  if (i >= a.M) return;
+  double old[16];
 #pragma unroll
-  for (int y = 0; y < 4; ++y)
+  for (int e = 0; e < 16; ++e) {
+    const int j = jb + 16 * (e >> 2) + 4 * (e & 3) + g;
+    old[e] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+  }
+  if (!aok) return;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = jb + 16 * y + 4 * r + g;
-      if (j < a.N) a.C[i + (int64_t)j * a.ldc] -= v[y * 4 + r];
-    }
+  for (int e = 0; e < 16; ++e) {
+    const int j = jb + 16 * (e >> 2) + 4 * (e & 3) + g;
+    if (j < a.N) a.C[i + (int64_t)j * a.ldc] = old[e] - v[e];
+  }
 }
 
-void launch_nn_sub(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb,
-                   int64_t M, int N, int K, const Scratch& s, hipStream_t st) {
-  if (M <= 0 || N <= 0 || K <= 0) return;
+NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                int N, int K, const Scratch& s) {
   NnArgs a{};
   a.C = C; a.ldc = ldc; a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
   a.M = M; a.N = N; a.K = K;
   a.tilesN = (N + 63) / 64;
   a.ntiles = (int)((M + 63) / 64) * a.tilesN;
-  a.vec = aligned16(B, ldb);
   a.part = s.part;
+  a.vec = aligned16(B, ldb);
+  // few tiles and a long reduction: split K so ~512 blocks (two per CU) run,
+  // each over at least 2 slabs
   int ns = 1;
-  if (a.ntiles < 512 && K >= 1024) {
-    ns = (int)std::min<int64_t>((768 + a.ntiles - 1) / a.ntiles, K / 512);
+  if (K > NK && a.ntiles < 512 && K >= 4 * NK) {
+    ns = (int)std::min<int64_t>((512 + a.ntiles - 1) / a.ntiles, K / (2 * NK));
     while (ns > 1 && (int64_t)ns * a.ntiles > s.npart) --ns;
   }
   int kchunk = (K + ns - 1) / ns;
-  kchunk = (kchunk + 15) / 16 * 16;
+  kchunk = (kchunk + NK - 1) / NK * NK;
   ns = (K + kchunk - 1) / kchunk;
   a.kchunk = kchunk;
   a.nsplit = ns;
-  if (ns > 1) {
-    hipLaunchKernelGGL(nn_kernel<true>, dim3(a.ntiles, ns), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(nn_reduce_kernel, dim3(a.ntiles), dim3(256), 0, st, a);
-  } else {
-    hipLaunchKernelGGL(nn_kernel<false>, dim3(a.ntiles, 1), dim3(256), 0, st, a);
+  return a;
+}
+
+template <int TAG>
+static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
+  if (a.K <= NK)
+    hipLaunchKernelGGL(nn1_kernel<TAG>, dim3(a.ntiles), dim3(256), 0, st, a);
+  else if (a.nsplit > 1)
+    hipLaunchKernelGGL((nn_kernel<true, TAG>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((nn_kernel<false, TAG>), dim3(a.ntiles, 1), dim3(256), 0, st, a);
+}
+
+void launch_nn_product(const NnArgs& a, int tag, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0 || a.K <= 0) return;
+  switch (tag) {
+    case TAG_TRAIL: nn_launch_tag<TAG_TRAIL>(a, st); break;
+    case TAG_REPROJ: nn_launch_tag<TAG_REPROJ>(a, st); break;
+    default: nn_launch_tag<TAG_PANEL>(a, st); break;
   }
+}
+
+void launch_nn_reduce(const NnArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0 || a.K <= NK || a.nsplit <= 1) return;
+  hipLaunchKernelGGL(nn_reduce_kernel, dim3(a.ntiles), dim3(256), 0, st, a);
 }
 
 }  // namespace cqr

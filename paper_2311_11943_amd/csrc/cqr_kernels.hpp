@@ -61,23 +61,58 @@ struct Scratch {
   double* R1;         // first-pass Cholesky factor (kLeaf x kLeaf)
 };
 
-// C (M x N) [= or +=] A^T B, A: K x M (lda), B: K x N (ldb).  The result is
-// stored to C (ldc); if C2 != nullptr it is also added into C2 (ldc2).
-void launch_tn(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K,
-               double* C, int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, hipStream_t st);
+// Kernel-instance tags: each use of a product kernel gets its own symbol, so
+// per-kernel profiles map onto the steps of the factorization.
+enum : int { TAG_TRAIL = 0, TAG_REPROJ = 1, TAG_PANEL = 2 };
 
-// Gram matrix W = P^T P of the w-column panel P (m' x w), then its upper
-// Cholesky factor.  pass 1: R1 <- chol, T <- R1^{-1}.  pass 2: R2 <- chol,
-// T <- R2^{-1}, Rout (ldr) <- R2 R1.  Breakdown sets info[0] = 1 + panel.
-void launch_gram_chol(const double* P, int64_t ldp, int64_t mrows, int w, int pass, double* Rout,
-                      int64_t ldr, int panel, const Scratch& s, hipStream_t st);
+// C (M x N) [= or +=] A^T B, A: K x M (lda), B: K x N (ldb), split over K.
+struct TnArgs {
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  int M, N; int64_t K;
+  int64_t kchunk; int nsplit; int tilesN; int ntiles;
+  double* C; int64_t ldc;
+  double* C2; int64_t ldc2;
+  double* part;
+  int vec;            // both operands 16-byte aligned with even leading dimensions
+};
+
+// Choose the split of C = A^T B (stored to C; added into C2 if C2 != nullptr).
+// force_split > 0 fixes the split count (capped by the partial capacity).
+TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
+                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0);
+// The product; with nsplit == 1 it stores C (and C2) itself, else partials.
+void launch_tn_product(const TnArgs& a, int tag, hipStream_t st);
+// Sum the partials into C (and C2) in split order (nsplit > 1 only).
+void launch_tn_reduce(const TnArgs& a, hipStream_t st);
+
+// C (M x N) -= A (M x K) B (K x N).
+struct NnArgs {
+  double* C; int64_t ldc;
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  int64_t M; int N; int K;
+  int kchunk; int nsplit; int tilesN; int ntiles;
+  int vec;            // B 16-byte aligned with even ldb (vector B loads)
+  double* part;
+};
+NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                int N, int K, const Scratch& s);
+void launch_nn_product(const NnArgs& a, int tag, hipStream_t st);
+void launch_nn_reduce(const NnArgs& a, hipStream_t st);   // nsplit > 1 only
+
+// Panel Gram matrix W = P^T P (P: m' x w, w <= kLeaf) as split partials into
+// s.part (or straight into s.W when not split).
+TnArgs gram_setup(const double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s);
+// Sum of the Gram partials into s.W (nsplit > 1 only).
+void launch_gram_sum(const TnArgs& g, const Scratch& s, hipStream_t st);
+// Upper Cholesky factor of s.W.  pass 1: R1 <- chol, T <- R1^{-1}.
+// pass 2: R2 <- chol, T <- R2^{-1}, Rout (ldr) <- R2 R1.  Breakdown sets
+// info[0] = 1 + panel.
+void launch_chol(int w, int pass, double* Rout, int64_t ldr, int panel, const Scratch& s, hipStream_t st);
 
 // P <- P T in place (T = s.T, w x w upper triangular), P is mrows x w.
 void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s, hipStream_t st);
-
-// C (M x N) -= A (M x K) B (K x N).
-void launch_nn_sub(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb,
-                   int64_t M, int N, int K, const Scratch& s, hipStream_t st);
 
 void launch_zero_ints(int* p, int n, hipStream_t st);
 void launch_fill_zero(double* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);

@@ -41,8 +41,9 @@ def test_library_exports_every_declared_symbol():
 def test_binding_wraps_every_declared_symbol():
     assert sorted(cqr.EXPORTS) == declared_functions()
     for name in cqr.EXPORTS:
-        if name != "coded_qr_status_string":
+        if name not in ("coded_qr_status_string", "coded_qr_hip_error_name"):
             assert callable(getattr(cqr, name))
+    assert cqr.hip_error_name() == "hipSuccess"
 
 
 def test_status_strings():
@@ -108,3 +109,19 @@ def test_oracle_not_imported_by_product_package():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
                 assert "oracle/" not in text, f
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Importing the binding first must not load a second HIP runtime next to
+    torch's (two HSA runtimes in one process leave the library without a
+    device)."""
+    import subprocess
+    import sys
+    code = ("from paper_2311_11943_amd import cqr\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
