@@ -29,7 +29,7 @@ struct cqr_plan_s {
   std::vector<double> gv;   // K_v x p_r row-major:  [G~_1  V~]
   std::vector<double> gh;   // p_c x K_h row-major
   int64_t npart = 0, nS = 0;
-  size_t off_part = 0, off_part2 = 0, off_S = 0, off_W = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
+  size_t off_part = 0, off_part2 = 0, off_S = 0, off_G = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
   // lookahead: second stream and its two events, created on first use on the
   // device current at that time
   hipStream_t side = nullptr;
@@ -198,7 +198,7 @@ cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws, bool second = false) {
   s.part = reinterpret_cast<double*>(b + (second ? p.off_part2 : p.off_part));
   s.npart = p.npart;
   s.S = reinterpret_cast<double*>(b + p.off_S);
-  s.W = reinterpret_cast<double*>(b + p.off_W);
+  s.G = reinterpret_cast<double*>(b + p.off_G);
   s.T = reinterpret_cast<double*>(b + p.off_T);
   s.R1 = reinterpret_cast<double*>(b + p.off_R1);
   return s;
@@ -292,9 +292,11 @@ int tag_of(int phase) {
 double partial_bytes(int nsplit, int ntiles) { return 8.0 * nsplit * ntiles * cqr::kTile * cqr::kTile; }
 
 void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N,
-        int64_t K, double* C, int64_t ldc, double* C2, int64_t ldc2, const cqr::Scratch& s, hipStream_t st) {
+        int64_t K, double* C, int64_t ldc, double* C2, int64_t ldc2, const cqr::Scratch& s, hipStream_t st,
+        int M2 = -1) {
   if (M <= 0 || N <= 0) return;
-  const cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s);
+  cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s);
+  if (M2 >= 0) a.M2 = M2;
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N);
   const double out = 8.0 * (double)M * N * (C2 ? 3.0 : 1.0);
   const int tag = tag_of(phase);
@@ -323,20 +325,24 @@ void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64
   }
 }
 
+void chol(cqr_plan_s& p, const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
+          int64_t ldx, double* Rbar, int panel, const cqr::Scratch& s, hipStream_t st) {
+  prof(p, PH_CHOL, 2.0 * w * w * w * (X ? 2.0 : 1.0), 8.0 * w * w * (pass == 1 ? 3.0 : (X ? 6.0 : 4.0)), st,
+       [&] { cqr::launch_chol(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s, st); });
+}
+
+void apply(cqr_plan_s& p, double* P, int64_t ldq, int w, const cqr::Scratch& s, hipStream_t st) {
+  const int64_t mp = p.mp;
+  prof(p, PH_APPLY, 2.0 * mp * w * w, 16.0 * mp * w, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
+}
+
 // One Cholesky-QR pass on the panel P (m' x w): Gram product (+ reduction),
 // Cholesky factor and inverse, then P <- P R^{-1}.
 void cholqr_pass(cqr_plan_s& p, double* P, int64_t ldq, int w, int pass, double* Rout, int64_t ldr, int panel,
                  const cqr::Scratch& s, hipStream_t st) {
-  const int64_t mp = p.mp;
-  const cqr::TnArgs g = cqr::gram_setup(P, ldq, mp, w, s);
-  const double gfl = 2.0 * mp * w * w, gby = 8.0 * mp * w;
-  prof(p, PH_GRAM, gfl, gby + partial_bytes(g.nsplit, 1), st, [&] { cqr::launch_tn_product(g, cqr::TAG_PANEL, st); });
-  if (g.nsplit > 1)
-    prof(p, PH_REDUCE, (g.nsplit - 1.0) * w * w, partial_bytes(g.nsplit, 1) + 8.0 * w * w, st,
-         [&] { cqr::launch_gram_sum(g, s, st); });
-  prof(p, PH_CHOL, 2.0 * w * w * w, 8.0 * w * w * (pass == 1 ? 3.0 : 4.0), st,
-       [&] { cqr::launch_chol(w, pass, Rout, ldr, panel, s, st); });
-  prof(p, PH_APPLY, gfl, 2 * gby, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
+  tn(p, PH_GRAM, P, ldq, P, ldq, w, w, p.mp, s.G, w, nullptr, 0, s, st);
+  chol(p, s.G, w, w, pass, Rout, ldr, nullptr, 0, nullptr, panel, s, st);
+  apply(p, P, ldq, w, s, st);
 }
 
 // Panel of w columns starting at column c: leaves of <= kLeaf columns are
@@ -436,12 +442,12 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   maxTiles = std::max(maxTiles, tiles(n - b, b));          // re-projection
   maxTiles = std::max(maxTiles, tiles(b, b));              // within-panel projection, Gram
   p->npart = std::max<int64_t>(1024, maxTiles);
-  p->nS = std::max<int64_t>(n * b, (int64_t)kLeaf * kLeaf);
+  p->nS = std::max<int64_t>(n * b, (int64_t)kLeaf * kLeaf);   // S with the fused Gram rows: c1 x b, c1 <= n
   size_t off = 256;
   p->off_part = off;  off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
   p->off_part2 = off; off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
   p->off_S = off;    off = align256(off + sizeof(double) * (size_t)p->nS);
-  p->off_W = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  p->off_G = off;    off = align256(off + sizeof(double) * 2 * kLeaf * kLeaf);
   p->off_T = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
   p->off_R1 = off;   off = align256(off + sizeof(double) * kLeaf * kLeaf);
   p->ws_bytes = off;
@@ -554,32 +560,76 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss);
   };
   bool side_pending = false;
+  // the caller's stream waits for the side stream's update of panel k-1
+  auto join_side = [&]() -> hipError_t {
+    if (!side_pending) return hipSuccess;
+    side_pending = false;
+    return hipStreamWaitEvent(st, p->ev_side, 0);
+  };
+  // panel k's update of columns [c1 + b, N) on the side stream
+  auto fork_side = [&](int64_t c0, int64_t from) -> hipError_t {
+    hipError_t e = hipEventRecord(p->ev_main, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_main, 0);
+    if (e != hipSuccess) return e;
+    trail(c0, from, N, s2, p->side);
+    e = hipEventRecord(p->ev_side, p->side);
+    if (e == hipSuccess) side_pending = true;
+    return e;
+  };
   for (int k = pb; k < pe; ++k) {
     const int64_t c0 = (int64_t)k * b, c1 = c0 + b;
     double* P = Q + c0 * ldq;
+    const bool next = la && k + 1 < pe;     // panel k+1 is factored in this call
+    if (b <= kLeaf) {
+      // First Cholesky-QR pass.  With re-projection its Gram matrix comes from
+      // the same product as the coefficients, [Q[:, :c0] | P]^T P: since the
+      // re-projection coefficients S are at rounding level, P^T P equals the
+      // Gram matrix of the re-projected panel up to rounding, and any residual
+      // difference is removed by the second pass.
+      const double* W1 = s.G;
+      int64_t ldw1 = b;
+      if (p->cfg.reproject && k > 0) {
+        // S = Q[:, :c0]^T P (rows < c0, also added into R[:c0, panel]);  P -= Q[:, :c0] S
+        tn(*p, PH_REPROJ_TN, Q, ldq, P, ldq, (int)c1, (int)b, mp, s.S, c1, R + c0 * ldr, ldr, s, st, (int)c0);
+        nn(*p, PH_REPROJ_NN, P, ldq, Q, ldq, s.S, c1, mp, (int)b, (int)c0, s, st);
+        W1 = s.S + c0;
+        ldw1 = c1;
+      } else {
+        tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, (int)b, mp, s.G, b, nullptr, 0, s, st);
+      }
+      chol(*p, W1, ldw1, (int)b, 1, nullptr, 0, nullptr, 0, nullptr, k, s, st);
+      apply(*p, P, ldq, (int)b, s, st);
+      // Second pass.  With lookahead the same product also gives
+      // X = P1^T Q_next, and the Cholesky kernel forms the next panel's
+      // coefficients R[panel, next] = (P1 R2^{-1})^T Q_next = R2^{-T} X.
+      // Q_next must first carry panel k-1's update from the side stream.
+      if (hipError_t e = join_side(); e != hipSuccess) return hip_fail(e);
+      tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, next ? 2 * (int)b : (int)b, mp, s.G, b, nullptr, 0, s, st);
+      chol(*p, s.G, b, (int)b, 2, R + c0 + c0 * ldr, ldr, next ? s.G + b * b : nullptr, b,
+           next ? R + c0 + c1 * ldr : nullptr, k, s, st);
+      apply(*p, P, ldq, (int)b, s, st);
+      if (next) {
+        // Q_next -= P R[panel, next]; the remaining columns on the side stream
+        nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st);
+        if (c1 + b < N)
+          if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
+      } else if (c1 < N) {
+        trail(c0, c1, N, s, st);
+      }
+      continue;
+    }
+    // Panels wider than a Cholesky-QR leaf: re-projection, recursive panel,
+    // then the update (the next panel's columns first with lookahead).
     if (p->cfg.reproject && k > 0) {
-      // S = Q[:, :c0]^T P;  R[:c0, panel] += S;  P -= Q[:, :c0] S
       tn(*p, PH_REPROJ_TN, Q, ldq, P, ldq, (int)c0, (int)b, mp, s.S, c0, R + c0 * ldr, ldr, s, st);
       nn(*p, PH_REPROJ_NN, P, ldq, Q, ldq, s.S, c0, mp, (int)b, (int)c0, s, st);
     }
     factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
     if (c1 >= N) continue;
-    // columns right of panel k carry panel k-1's update from the side stream
-    if (side_pending) {
-      const hipError_t e = hipStreamWaitEvent(st, p->ev_side, 0);
-      if (e != hipSuccess) return hip_fail(e);
-    }
-    side_pending = false;
-    if (la && k + 1 < pe && c1 + b < N) {
-      // lookahead: the next panel's columns now, the rest on the side stream
+    if (hipError_t e = join_side(); e != hipSuccess) return hip_fail(e);
+    if (next && c1 + b < N) {
       trail(c0, c1, c1 + b, s, st);
-      hipError_t e = hipEventRecord(p->ev_main, st);
-      if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_main, 0);
-      if (e != hipSuccess) return hip_fail(e);
-      trail(c0, c1 + b, N, s2, p->side);
-      e = hipEventRecord(p->ev_side, p->side);
-      if (e != hipSuccess) return hip_fail(e);
-      side_pending = true;
+      if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
     } else {
       trail(c0, c1, N, s, st);
     }

@@ -36,34 +36,28 @@ __device__ __forceinline__ int64_t part_off(int sp, int ntiles, int tile, int wa
   return (((int64_t)sp * ntiles + tile) * 4 + wave) * 1024;
 }
 
-// Sum the 16 per-lane values of `nsplit` partial tiles in split order.  The
-// loads of four splits are issued before they are added, so the single pass
-// is bandwidth- rather than latency-bound; the addition order stays 0, 1, 2...
-__device__ __forceinline__ void sum_partials(const double* part, int nsplit, int ntiles, int tile, int wave,
-                                             int lane, double (&v)[16]) {
+// Sum over splits of four element slots q = 4 qg + u (u < 4) of one wave's
+// partial tiles, lane `lane`, in split order.  Batches of 16 splits have all
+// their loads issued before the first addition.
+__device__ __forceinline__ void sum_partials4(const double* part, int nsplit, int ntiles, int tile, int wave,
+                                              int qg, int lane, double (&v)[4]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = 0.0;
-  int sp = 0;
-  for (; sp + 4 <= nsplit; sp += 4) {
-    double t[4][16];
+  for (int u = 0; u < 4; ++u) v[u] = 0.0;
+  const double* base = part + part_off(0, ntiles, tile, wave) + 4 * qg * 64 + lane;
+  const int64_t sstride = (int64_t)ntiles * 4 * 1024;
+  for (int sp0 = 0; sp0 < nsplit; sp0 += 16) {
+    double t[16][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double* p = part + part_off(sp + u, ntiles, tile, wave);
+    for (int k = 0; k < 16; ++k) {
+      const int sp = std::min(sp0 + k, nsplit - 1);       // clamped: extra loads are discarded
 #pragma unroll
-      for (int q = 0; q < 16; ++q) t[u][q] = p[q * 64 + lane];
+      for (int u = 0; u < 4; ++u) t[k][u] = base[sp * sstride + u * 64];
     }
-    // keep the 64 loads ahead of the additions (the scheduler would
-    // otherwise pair each load with its add and wait on it)
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int k = 0; k < 16; ++k)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] += t[u][q];
-  }
-  for (; sp < nsplit; ++sp) {
-    const double* p = part + part_off(sp, ntiles, tile, wave);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] += p[q * 64 + lane];
+      for (int u = 0; u < 4; ++u) v[u] += (sp0 + k < nsplit) ? t[k][u] : 0.0;
   }
 }
 
@@ -81,15 +75,15 @@ constexpr int LDP = KC + 2;      // padded LDS column (doubles)
 // Store a wave's 32 x 32 quadrant (16 values per lane, element (x, y, r) at
 // row i0 + 16x + li, column j0 + 16y + 4r + g) to C, and add it into C2 if
 // given; the C2 loads are all issued before any store.
-__device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C2, int64_t ldc2, int M, int N,
-                                               int i0, int j0, int li, int g, const double (&v)[16]) {
+__device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C2, int64_t ldc2, int M, int M2,
+                                               int N, int i0, int j0, int li, int g, const double (&v)[16]) {
   double old[16];
   if (C2) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
       const int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
-      old[e] = (i < M && j < N) ? C2[i + (int64_t)j * ldc2] : 0.0;
+      old[e] = (i < M2 && j < N) ? C2[i + (int64_t)j * ldc2] : 0.0;
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -99,7 +93,7 @@ __device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C
     const int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
     if (i < M && j < N) {
       C[i + (int64_t)j * ldc] = v[e];
-      if (C2) C2[i + (int64_t)j * ldc2] = old[e] + v[e];
+      if (C2 && i < M2) C2[i + (int64_t)j * ldc2] = old[e] + v[e];
     }
   }
 }
@@ -120,7 +114,7 @@ __device__ __forceinline__ void tn_store(const TnArgs& a, const v4d (&acc)[2][2]
   double v[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = acc[e >> 3][(e >> 2) & 1][e & 3];
-  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.N, i0, j0, li, g, v);
+  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.M2, a.N, i0, j0, li, g, v);
 }
 
 template <int TAG>
@@ -294,15 +288,33 @@ __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
   tn_store(a, acc, tile, split, wave, lane, i0, j0);
 }
 
-// Sum the split partials of every tile in split order; write C (and C2 +=).
+// Sum the split partials in split order; write C (and C2 +=).  One block per
+// wave quadrant of a tile, thread (qg, lane) owns 4 of the lane's 16 values.
 __global__ __launch_bounds__(256) void tn_reduce_kernel(TnArgs a) {
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x >> 2, wave = blockIdx.x & 3;
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
-  const int i0 = tm * 64 + (wave & 1) * 32, j0 = tn * 64 + (wave >> 1) * 32;
-  double v[16];
-  sum_partials(a.part, a.nsplit, a.ntiles, tile, wave, lane, v);
-  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.N, i0, j0, li, g, v);
+  const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int i = tm * 64 + (wave & 1) * 32 + 16 * (qg >> 1) + li;
+  const int j0 = tn * 64 + (wave >> 1) * 32 + 16 * (qg & 1) + g;     // column of u = 0; u adds 4u
+  double old[4];
+  if (a.C2) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 4 * u;
+      old[u] = (i < a.M2 && j < a.N) ? a.C2[i + (int64_t)j * a.ldc2] : 0.0;
+    }
+  }
+  double v[4];
+  sum_partials4(a.part, a.nsplit, a.ntiles, tile, wave, qg, lane, v);
+  if (i >= a.M) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 4 * u;
+    if (j < a.N) {
+      a.C[i + (int64_t)j * a.ldc] = v[u];
+      if (a.C2 && i < a.M2) a.C2[i + (int64_t)j * a.ldc2] = old[u] + v[u];
+    }
+  }
 }
 
 static bool aligned16(const void* p, int64_t ld) {
@@ -322,7 +334,7 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
                 int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split) {
   TnArgs a{};
   a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
-  a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2;
+  a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2; a.M2 = M;
   const int tilesM = (M + kTile - 1) / kTile, tilesN = (N + kTile - 1) / kTile;
   const int tiles = tilesM * tilesN;
   int ns = force_split > 0 ? force_split : pick_split(tiles, K, s.npart);
@@ -352,47 +364,24 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
 
 void launch_tn_reduce(const TnArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.nsplit <= 1) return;
-  hipLaunchKernelGGL(tn_reduce_kernel, dim3(a.ntiles), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(tn_reduce_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a);
 }
 
 // --------------------------------------------------------------------------
-// Gram matrix of a panel leaf (w <= kLeaf columns) and its upper Cholesky
-// factor.  The split-K partial tiles are first summed by gram_sum_kernel
-// (16 blocks, one 256-entry slice each, split order), then one wavefront
-// factors W: lane t keeps column t of W in registers and the rows of R are
-// exchanged through LDS, so the 64 sequential steps need no block barrier.
-// pass 1: R1 <- chol(W), T <- R1^{-1}.  pass 2: T <- R2^{-1}, Rout <- R2 R1.
-// A non-positive pivot sets info[0] = 1 + panel (first occurrence kept) and
-// the factorization continues with pivot 1.
+// Upper Cholesky factor of a panel leaf's Gram matrix W (w <= kLeaf), its
+// inverse, and on the second pass R2 R1 and the lookahead coefficients T^T X.
+// One block of four waves (see chol_aug for the elimination).  A
+// non-positive pivot sets info[0] = 1 + panel (first occurrence kept) and the
+// factorization continues with pivot 1.
 // --------------------------------------------------------------------------
 struct CholArgs {
-  const double* part; int nsplit;
-  double* W;               // w x w Gram matrix (ld w): written by the sum kernel or the product kernel
+  const double* W; int64_t ldw;     // w x w Gram matrix
   int w, pass, panel;
   double* T; double* R1; double* Rout; int64_t ldr; int* info;
+  const double* X; int64_t ldx;     // pass 2, optional: w x w product P1^T Q_next
+  double* Rbar;                     // T^T X (ld ldr)
 };
 
-// W entry e = i + j*w  <-  sum over splits of the partial element mapped to (i, j)
-__global__ __launch_bounds__(256) void gram_sum_kernel(CholArgs a) {
-  const int e = blockIdx.x * 256 + threadIdx.x;      // 0 .. 4095 over the 64 x 64 tile
-  const int i = e & 63, j = e >> 6;
-  // inverse of the (wave, q, lane) -> (i, j) map of the product kernel
-  const int wave = (i >> 5) | ((j >> 5) << 1);
-  const int x = (i >> 4) & 1, y = (j >> 4) & 1, li = i & 15, r = (j & 15) >> 2, g = j & 3;
-  const int q = (x * 2 + y) * 4 + r, lane = g * 16 + li;
-  const double* p = a.part + part_off(0, 1, 0, wave) + q * 64 + lane;
-  double v = 0.0;
-  int sp = 0;
-  for (; sp + 8 <= a.nsplit; sp += 8) {
-    double t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(sp + u) * 4096];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v += t[u];
-  }
-  for (; sp < a.nsplit; ++sp) v += p[(int64_t)sp * 4096];
-  if (i < a.w && j < a.w) a.W[i + j * a.w] = v;
-}
 
 // 1/sqrt(x) to full double precision: hardware estimate plus one Newton step.
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -475,21 +464,23 @@ __device__ __forceinline__ void chol_aug(int tid, double (*rowW)[kLeaf], double 
   __syncthreads();
 }
 
-// C = A B for 64 x 64 LDS matrices (row-major, padded), upper triangular A
-// and B; wave v computes rows 16v..16v+15 and stores C[i][j] (i, j < w) into
-// the column-major global matrix out (ld ldo).
-__device__ __forceinline__ void tri_mm_store(int tid, const double (*Al)[kLeaf + 1], const double (*Bl)[kLeaf + 1],
+// C = op(A) B for 64 x 64 LDS matrices (row-major, padded): op(A) = A, or
+// A^T when TRANS_A.  UPPER: A and B upper triangular (C[i][j] needs only
+// k in [i, j]; k blocks left of the row block are skipped).  Wave v computes
+// rows 16v..16v+15 and stores C[i][j] (i, j < w) into the column-major global
+// matrix out (ld ldo).
+template <bool TRANS_A, bool UPPER>
+__device__ __forceinline__ void lds_mm_store(int tid, const double (*Al)[kLeaf + 1], const double (*Bl)[kLeaf + 1],
                                              int w, double* out, int64_t ldo) {
   const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
   v4d acc[4];
 #pragma unroll
   for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
-  // C[i][j] needs k in [i, j]: skip k blocks left of the row block
-  for (int k0 = 16 * wave; k0 < kLeaf; k0 += 16) {
+  for (int k0 = UPPER ? 16 * wave : 0; k0 < kLeaf; k0 += 16) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = k0 + 4 * g + s;
-      const double xa = Al[16 * wave + li][k];
+      const double xa = TRANS_A ? Al[k][16 * wave + li] : Al[16 * wave + li][k];
 #pragma unroll
       for (int y = 0; y < 4; ++y) acc[y] = mfma(Bl[k][16 * y + li], xa, acc[y]);
     }
@@ -507,24 +498,27 @@ __device__ __forceinline__ void tri_mm_store(int tid, const double (*Al)[kLeaf +
 __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   __shared__ double Rl[kLeaf][kLeaf + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
+  __shared__ double Xl[kLeaf][kLeaf + 1];
   __shared__ double rowW[2][kLeaf];
   __shared__ double rowZ[2][kLeaf];
   __shared__ int s_exact, s_bad;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, w = a.w;
   if (tid == 0) { s_exact = (a.pass == 1); s_bad = 0; }
-  // W (w x w, column-major) into Rl, identity-padded: all loads issued first
+  // W (w x w) into Rl, identity-padded, and X into Xl: all loads issued first
   {
-    double v[16];
+    double v[16], xv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = ty + 4 * q;   // column
-      v[q] = (tx < w && k < w) ? a.W[tx + (int64_t)k * w] : (tx == k ? 1.0 : 0.0);
+      v[q] = (tx < w && k < w) ? a.W[tx + (int64_t)k * a.ldw] : (tx == k ? 1.0 : 0.0);
+      xv[q] = (a.X && tx < w && k < w) ? a.X[tx + (int64_t)k * a.ldx] : 0.0;
     }
     bool far = false;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = ty + 4 * q;
       Rl[tx][k] = v[q];
+      Xl[tx][k] = xv[q];
       far |= !(fabs(v[q] - (tx == k ? 1.0 : 0.0)) <= 1e-8);
     }
     __syncthreads();
@@ -564,6 +558,8 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
     }
   }
   if (a.pass == 2) {
+    // the next panel's update coefficients: (P1 T)^T Q_next = T^T X
+    if (a.X) lds_mm_store<true, false>(tid, Tl, Xl, w, a.Rbar, a.ldr);
     // R_panel = R2 R1 with R1 staged in Tl (T is stored)
     __syncthreads();
 #pragma unroll
@@ -572,30 +568,18 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
       Tl[tx][k] = (tx < w && k < w) ? a.R1[tx + k * w] : (tx == k ? 1.0 : 0.0);
     }
     __syncthreads();
-    tri_mm_store(tid, Rl, Tl, w, a.Rout, a.ldr);
+    lds_mm_store<false, true>(tid, Rl, Tl, w, a.Rout, a.ldr);
   }
   if (tid == 0 && s_bad && *a.info == 0) *a.info = 1 + a.panel;
 }
 
-TnArgs gram_setup(const double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s) {
-  // one output tile: split the rows finely (>= 128 per block, at most 64 blocks)
-  const int fs = (int)std::max<int64_t>(1, std::min<int64_t>(64, mrows / 128));
-  TnArgs g = tn_setup(P, ldp, P, ldp, w, w, mrows, s.W, w, nullptr, 0, s, fs);
-  return g;
-}
-
-void launch_gram_sum(const TnArgs& g, const Scratch& s, hipStream_t st) {
-  if (g.nsplit <= 1) return;
+void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st) {
   CholArgs c{};
-  c.part = s.part; c.nsplit = g.nsplit; c.W = s.W; c.w = g.M;
-  hipLaunchKernelGGL(gram_sum_kernel, dim3(16), dim3(256), 0, st, c);
-}
-
-void launch_chol(int w, int pass, double* Rout, int64_t ldr, int panel, const Scratch& s, hipStream_t st) {
-  CholArgs c{};
-  c.part = s.part; c.nsplit = 1; c.W = s.W;
+  c.W = W; c.ldw = ldw;
   c.w = w; c.pass = pass; c.panel = panel;
   c.T = s.T; c.R1 = s.R1; c.Rout = Rout; c.ldr = ldr; c.info = s.info;
+  c.X = X; c.ldx = ldx; c.Rbar = Rbar;
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, c);
 }
 
@@ -862,27 +846,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     }
 }
 
+// C -= sum of the split partials (split order).  One block per wave of a
+// tile, thread (qg, lane) owns the lane's 4 values of column block qg.
 __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x >> 2, wave = blockIdx.x & 3;
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int64_t i = (int64_t)tm * 64 + wave * 16 + li;
-  const int jb = tn * 64;
+  const int j0 = tn * 64 + 16 * qg + g;
   const bool aok = i < a.M;
   const int64_t ic = aok ? i : 0;
-  double v[16];
-  sum_partials(a.part, a.nsplit, a.ntiles, tile, wave, lane, v);
-  double old[16];
+  double old[4];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int j = jb + 16 * (e >> 2) + 4 * (e & 3) + g;
-    old[e] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 4 * u;
+    old[u] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
   }
+  double v[4];
+  sum_partials4(a.part, a.nsplit, a.ntiles, tile, wave, qg, lane, v);
   if (!aok) return;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int j = jb + 16 * (e >> 2) + 4 * (e & 3) + g;
-    if (j < a.N) a.C[i + (int64_t)j * a.ldc] = old[e] - v[e];
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + 4 * u;
+    if (j < a.N) a.C[i + (int64_t)j * a.ldc] = old[u] - v[u];
   }
 }
 
@@ -931,7 +917,7 @@ void launch_nn_product(const NnArgs& a, int tag, hipStream_t st) {
 
 void launch_nn_reduce(const NnArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.K <= NK || a.nsplit <= 1) return;
-  hipLaunchKernelGGL(nn_reduce_kernel, dim3(a.ntiles), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(nn_reduce_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a);
 }
 
 }  // namespace cqr

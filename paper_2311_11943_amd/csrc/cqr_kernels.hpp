@@ -55,8 +55,8 @@ struct Scratch {
   int* info;          // [0]: breakdown flag (0 or 1 + panel)
   double* part;       // split-K partial tiles
   int64_t npart;      // capacity in tiles (of kTile*kTile doubles)
-  double* S;          // projection coefficients
-  double* W;          // Gram matrix (kLeaf x kLeaf)
+  double* S;          // projection coefficients (and the fused first-pass Gram)
+  double* G;          // second-pass Gram and lookahead product (kLeaf x 2 kLeaf)
   double* T;          // inverse Cholesky factor (kLeaf x kLeaf)
   double* R1;         // first-pass Cholesky factor (kLeaf x kLeaf)
 };
@@ -73,11 +73,13 @@ struct TnArgs {
   int64_t kchunk; int nsplit; int tilesN; int ntiles;
   double* C; int64_t ldc;
   double* C2; int64_t ldc2;
+  int M2;             // only rows i < M2 are added into C2
   double* part;
   int vec;            // both operands 16-byte aligned with even leading dimensions
 };
 
-// Choose the split of C = A^T B (stored to C; added into C2 if C2 != nullptr).
+// Choose the split of C = A^T B (stored to C; rows below M2 -- all rows
+// unless changed -- also added into C2 if C2 != nullptr).
 // force_split > 0 fixes the split count (capped by the partial capacity).
 TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
                 int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0);
@@ -101,15 +103,12 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
 void launch_nn_product(const NnArgs& a, int tag, hipStream_t st);
 void launch_nn_reduce(const NnArgs& a, hipStream_t st);   // nsplit > 1 only
 
-// Panel Gram matrix W = P^T P (P: m' x w, w <= kLeaf) as split partials into
-// s.part (or straight into s.W when not split).
-TnArgs gram_setup(const double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s);
-// Sum of the Gram partials into s.W (nsplit > 1 only).
-void launch_gram_sum(const TnArgs& g, const Scratch& s, hipStream_t st);
-// Upper Cholesky factor of s.W.  pass 1: R1 <- chol, T <- R1^{-1}.
-// pass 2: R2 <- chol, T <- R2^{-1}, Rout (ldr) <- R2 R1.  Breakdown sets
-// info[0] = 1 + panel.
-void launch_chol(int w, int pass, double* Rout, int64_t ldr, int panel, const Scratch& s, hipStream_t st);
+// Upper Cholesky factor of the panel Gram matrix W (w x w, ld ldw, w <= kLeaf).
+// pass 1: R1 <- chol(W), T <- R1^{-1}.  pass 2: R2 <- chol(W), T <- R2^{-1},
+// Rout (ldr) <- R2 R1, and, if X != nullptr, Rbar (ldr) <- T^T X (X: w x w,
+// ld ldx).  Breakdown sets info[0] = 1 + panel.
+void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st);
 
 // P <- P T in place (T = s.T, w x w upper triangular), P is mrows x w.
 void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s, hipStream_t st);
