@@ -59,10 +59,12 @@ typedef struct {
   int32_t reproject;   /* 1: re-project each panel against all earlier Q columns
                           before factoring it (default); 0: the paper's PBMGS */
   int32_t precision;   /* cqr_precision */
-  int32_t lookahead;   /* 1: while panel k+1 is factored on the caller's stream, a
-                          second stream owned by the plan applies panel k's update
-                          to the columns right of panel k+1 (same operations;
-                          split products may sum in another order); 0: one stream */
+  int32_t lookahead;   /* 1: the panel chain runs on a plan-owned stream while a
+                          second plan-owned stream applies each panel's update to
+                          the columns right of the next panel (same operations;
+                          split products may sum in another order); both fork
+                          from and join back to the caller's stream within each
+                          call.  0: everything on the caller's stream */
 } cqr_config;
 
 typedef struct cqr_plan_s* cqr_plan;

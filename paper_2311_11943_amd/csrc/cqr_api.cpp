@@ -30,10 +30,10 @@ struct cqr_plan_s {
   std::vector<double> gh;   // p_c x K_h row-major
   int64_t npart = 0, nS = 0;
   size_t off_part = 0, off_part2 = 0, off_S = 0, off_G = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
-  // lookahead: second stream and its two events, created on first use on the
-  // device current at that time
-  hipStream_t side = nullptr;
-  hipEvent_t ev_main = nullptr, ev_side = nullptr;
+  // lookahead: the panel chain's stream, the update stream and three events,
+  // created on first use on the device current at that time
+  hipStream_t chain = nullptr, side = nullptr;
+  hipEvent_t ev_main = nullptr, ev_side = nullptr, ev_chain = nullptr;
   int side_dev = -1;
   // opt-in per-launch timing
   struct Rec { int phase; hipEvent_t a, b; double flops, bytes; };
@@ -249,23 +249,29 @@ void prof(cqr_plan_s& p, int phase, double flops, double bytes, hipStream_t st, 
 void side_release(cqr_plan_s& p) {
   if (p.ev_main) (void)hipEventDestroy(p.ev_main);
   if (p.ev_side) (void)hipEventDestroy(p.ev_side);
+  if (p.ev_chain) (void)hipEventDestroy(p.ev_chain);
   if (p.side) (void)hipStreamDestroy(p.side);
-  p.side = nullptr;
-  p.ev_main = p.ev_side = nullptr;
+  if (p.chain) (void)hipStreamDestroy(p.chain);
+  p.side = p.chain = nullptr;
+  p.ev_main = p.ev_side = p.ev_chain = nullptr;
   p.side_dev = -1;
 }
 
-// The lookahead stream (default priority, no implicit synchronization with
-// the null stream) and its events on the current device.
+// The lookahead streams (default priority, no implicit synchronization with
+// the null stream) and their events on the current device.
 bool side_ready(cqr_plan_s& p) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   if (p.side && p.side_dev == dev) return true;
   side_release(p);
-  if (hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p.ev_main, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p.ev_side, hipEventDisableTiming) != hipSuccess) {
+  const bool ok = hipStreamCreateWithFlags(&p.chain, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&p.ev_main, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&p.ev_side, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&p.ev_chain, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     side_release(p);
+    (void)hipGetLastError();
     return false;
   }
   p.side_dev = dev;
@@ -546,11 +552,15 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     prof(*p, PH_OTHER, 0.0, 8.0 * n * N, st, [&] { cqr::launch_fill_zero(R, ldr, n, N, st); });
   }
   const bool la = p->cfg.lookahead && pe - pb > 1 && side_ready(*p);
+  const hipStream_t caller = st;
   if (la) {
-    // the side stream starts after everything already queued on `st`
-    hipError_t e = hipEventRecord(p->ev_main, st);
+    // both lookahead streams start after everything already queued on the
+    // caller's stream; the chain runs on its own stream from here on
+    hipError_t e = hipEventRecord(p->ev_main, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->chain, p->ev_main, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_main, 0);
     if (e != hipSuccess) return hip_fail(e);
+    st = p->chain;
   }
   // Panel k's update of columns [from, N):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
   auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
@@ -634,8 +644,11 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       trail(c0, c1, N, s, st);
     }
   }
-  if (side_pending) {
-    const hipError_t e = hipStreamWaitEvent(st, p->ev_side, 0);
+  if (hipError_t e = join_side(); e != hipSuccess) return hip_fail(e);
+  if (la) {
+    // the caller's stream waits for the chain (which has joined the updates)
+    hipError_t e = hipEventRecord(p->ev_chain, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(caller, p->ev_chain, 0);
     if (e != hipSuccess) return hip_fail(e);
   }
   return hip_status();
