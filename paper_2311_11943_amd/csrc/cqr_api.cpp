@@ -562,7 +562,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     if (e != hipSuccess) return hip_fail(e);
     st = p->chain;
   }
-  // Panel k's update of columns [from, N):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
+  // Panel k's update of columns [from, to):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
   auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
     double* Rb = R + c0 + from * ldr;
     const double* P = Q + c0 * ldq;

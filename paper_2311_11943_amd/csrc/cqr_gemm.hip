@@ -495,30 +495,64 @@ __device__ __forceinline__ void lds_mm_store(int tid, const double (*Al)[kLeaf +
     }
 }
 
+// C = T^T X with T (64 x 64, upper triangular, row-major LDS) and X (w x w,
+// column-major global, ld ldx, read straight from L2); C[i][j] (i, j < w) to
+// the column-major global matrix out (ld ldo).  Wave v computes rows
+// 16v..16v+15; (T^T)[i][k] = T[k][i] vanishes for k > i.
+__device__ __forceinline__ void tmul_global_store(int tid, const double (*Tl)[kLeaf + 1], const double* X,
+                                                  int64_t ldx, int w, double* out, int64_t ldo) {
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  v4d acc[4];
+#pragma unroll
+  for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
+  for (int k0 = 0; k0 < 16 * wave + 16; k0 += 16) {
+    double xb[4][4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * g + s, j = 16 * y + li;
+        xb[y][s] = (k < w && j < w) ? X[k + (int64_t)j * ldx] : 0.0;
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      const double xa = Tl[k][16 * wave + li];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[y] = mfma(xb[y][s], xa, acc[y]);
+    }
+  }
+  const int i = 16 * wave + li;
+#pragma unroll
+  for (int y = 0; y < 4; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * y + 4 * r + g;
+      if (i < w && j < w) out[i + (int64_t)j * ldo] = acc[y][r];
+    }
+}
+
 __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   __shared__ double Rl[kLeaf][kLeaf + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
-  __shared__ double Xl[kLeaf][kLeaf + 1];
   __shared__ double rowW[2][kLeaf];
   __shared__ double rowZ[2][kLeaf];
   __shared__ int s_exact, s_bad;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, w = a.w;
   if (tid == 0) { s_exact = (a.pass == 1); s_bad = 0; }
-  // W (w x w) into Rl, identity-padded, and X into Xl: all loads issued first
+  // W (w x w) into Rl, identity-padded: all loads issued first
   {
-    double v[16], xv[16];
+    double v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = ty + 4 * q;   // column
       v[q] = (tx < w && k < w) ? a.W[tx + (int64_t)k * a.ldw] : (tx == k ? 1.0 : 0.0);
-      xv[q] = (a.X && tx < w && k < w) ? a.X[tx + (int64_t)k * a.ldx] : 0.0;
     }
     bool far = false;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = ty + 4 * q;
       Rl[tx][k] = v[q];
-      Xl[tx][k] = xv[q];
       far |= !(fabs(v[q] - (tx == k ? 1.0 : 0.0)) <= 1e-8);
     }
     __syncthreads();
@@ -559,7 +593,7 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   }
   if (a.pass == 2) {
     // the next panel's update coefficients: (P1 T)^T Q_next = T^T X
-    if (a.X) lds_mm_store<true, false>(tid, Tl, Xl, w, a.Rbar, a.ldr);
+    if (a.X) tmul_global_store(tid, Tl, a.X, a.ldx, w, a.Rbar, a.ldr);
     // R_panel = R2 R1 with R1 staged in Tl (T is stored)
     __syncthreads();
 #pragma unroll
