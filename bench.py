@@ -40,6 +40,9 @@ WORKLOADS = {
     "c2": dict(n=4096, pr=8, K=2, b=64, storage="in", kind="random", nfail=2,
                desc="n=4096 Gaussian FP64, 8x8 grid (512x512 blocks), b=64, K=2 in-node checksums (f_tol=1), "
                     "2 random node failures at random panels"),
+    "c3": dict(n=16384, pr=8, K=4, b=128, storage="out", kind="revdiag", nfail=4,
+               desc="n=16384 Gaussian FP64, 8x8 grid (2048x2048 blocks), b=128, K=4 out-of-node (f_tol=4), "
+                    "reverse-diagonal failures every 16 panels"),
     "c5": dict(n=32768, pr=16, K=8, b=256, storage="in", kind="revdiag", nfail=4,
                desc="n=32768 Gaussian FP64, 16x16 grid (2048x2048 blocks), b=256, K=8 in-node (f_tol=4), "
                     "reverse-diagonal failures every 16 panels"),
@@ -59,6 +62,7 @@ KERNEL_OF = {
     "trailing_product": "tn_lds_kernel<0>", "trailing_update": "nn1_kernel<0>",
     "split_reduce": "tn_reduce_kernel / nn_reduce_kernel / gram_sum_kernel", "recover": "line_kernel",
     "postorth": "postorth_kernel", "erase": "erase_kernel", "other": "zero_ints_kernel / fill_zero_kernel",
+    "panel_reencode": "encode_rows_kernel (one panel)",
 }
 
 
@@ -81,6 +85,29 @@ def workload_inputs(name: str, ftol: int, seed: int = 0) -> dict:
         # (events sharing a panel hit distinct grid rows and columns)
         "schedule": synth.draw_schedule(w["kind"], n // b, pr, pr, seed, nfail=w["nfail"], every=16, f=ftol),
     }
+
+
+def conditioned_input(n: int, cond: float, seed: int, dev) -> np.ndarray:
+    """A = U diag(s) V^T with Haar U, V (sign-fixed QR of seeded Gaussians) and
+    s_i = cond^(-i/(n-1)).  Small sizes use the shared numpy generator; large
+    ones run the QRs on the device (input generation only, outside timing)."""
+    if n <= 4096:
+        return synth.conditioned(n, cond, seed)
+    import torch
+    g = torch.Generator().manual_seed(seed)
+
+    def haar():
+        z = torch.randn(n, n, generator=g, dtype=torch.float64).to(dev)
+        qm, rm = torch.linalg.qr(z)
+        return qm * torch.sign(torch.diagonal(rm))
+
+    u, v = haar(), haar()
+    s = cond ** (-torch.arange(n, dtype=torch.float64, device=dev) / max(n - 1, 1))
+    a = (u * s) @ v.T
+    out = np.asfortranarray(a.cpu().numpy())
+    del u, v, a
+    torch.cuda.empty_cache()
+    return out
 
 
 def source_hash() -> str:
@@ -120,6 +147,11 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, launch one plain copy kernel of 512 MiB (y = 2x) as the reference for "
                          "HBM byte counters")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"),
+                    help="fp32: trailing-update products in FP32 on MFMA (everything else FP64)")
+    ap.add_argument("--cond", type=float, default=0.0,
+                    help="> 0: A = U diag(s) V^T with Haar U, V and log-spaced s of this condition number "
+                         "instead of a Gaussian A")
     ap.add_argument("--lookahead", type=int, default=1, choices=(0, 1),
                     help="1: overlap the next panel with the trailing update on a second stream")
     args = ap.parse_args()
@@ -136,13 +168,16 @@ def main():
     w = WORKLOADS[args.workload]
     n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
     storage = cqr.CQR_IN_NODE if w["storage"] == "in" else cqr.CQR_OUT_OF_NODE
-    cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead)
+    prec = cqr.CQR_TRAIL_FP32 if args.precision == "fp32" else cqr.CQR_FP64
+    cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead, precision=prec)
     v = synth.q_generator_draws(K, pr, args.seed)
     gh = synth.r_generator_draws(pr, K, args.seed)
     q = cqr.CodedQR(cfg, v, gh, dev)
     ftol = q.ftol
     inp = workload_inputs(args.workload, ftol, args.seed)
     A_host, rhs_host, sched = inp["A"], inp["rhs"], inp["schedule"]
+    if args.cond > 0:
+        A_host = conditioned_input(n, args.cond, args.seed, dev)
     A = cqr.to_device_colmajor(A_host, dev)
     B = cqr.to_device_colmajor(rhs_host, dev)
     At, R = q.alloc()
@@ -189,11 +224,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 trailing update / f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "n": n, "grid": f"{pr}x{pr}", "b": b,
                    "K": K, "f_tol": ftol, "storage": w["storage"], "panel": "CholQR2 (block CGS2) + re-projection",
-                   "lookahead": args.lookahead,
+                   "lookahead": args.lookahead, "precision": args.precision,
+                   "input": "gaussian" if args.cond <= 0 else f"U diag(s) V^T, cond {args.cond:g}",
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched],
                    "model_flops": F, "wall_s_timed": round(wall, 3)},
     }
@@ -228,7 +264,7 @@ def main():
         t_fac = timed(lambda: (enc(), fac()))  - t_enc
         t_post = timed(lambda: q.postorth(At, Qpost, B, Bpost))
         # uncoded: same library, K = 0
-        cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead)
+        cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead, precision=prec)
         qu = cqr.CodedQR(cu, None, None, dev)
         Au, Ru = qu.alloc()
 
@@ -269,9 +305,11 @@ def main():
         r = rep[dom]
         if dom in MFMA_PHASES:
             ach = r["flops"] / (r["ms"] * 1e-3) / 1e12
+            # the trailing products run on FP32 MFMA in the mixed form, everything else on FP64
+            pk = PEAK["fp32_mfma_tflops" if args.precision == "fp32" and dom == "trailing_product"
+                      else "fp64_mfma_tflops"]
             roof = {"kernel": KERNEL_OF[dom], "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
-                    "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK["fp64_mfma_tflops"], 4)}
+                    "peak": pk, "unit": "TFLOP/s", "frac": round(ach / pk, 4)}
         else:
             ach = r["bytes"] / (r["ms"] * 1e-3) / 1e9
             roof = {"kernel": KERNEL_OF[dom], "phase": dom, "bound": "hbm", "achieved": round(ach, 1),

@@ -46,8 +46,18 @@ typedef enum {
 
 typedef enum { CQR_OUT_OF_NODE = 0, CQR_IN_NODE = 1 } cqr_storage;
 
-/* Arithmetic of the trailing-update products (panel norms, R diagonals,
- * recovery solve and post-orthogonalization stay FP64 in every mode). */
+/* Arithmetic of the trailing-update products R_bar = Qbar^T Q_t and
+ * Q_t -= Qbar R_bar.  CQR_TRAIL_FP32: operands rounded to FP32, products and
+ * accumulation on FP32 MFMA, results stored back into the FP64 arrays.  The
+ * re-projection (the second Gram-Schmidt pass), the panel factorization, the
+ * recovery solve and the post-orthogonalization stay FP64 in every mode, so
+ * the FP64 second pass wins back the orthogonality the FP32 first pass loses.
+ * In CQR_TRAIL_FP32 each panel's checksum rows are re-derived from its
+ * systematic rows in FP64 before the panel is factored (FP32 rounding is not
+ * linear, so the updates alone would let Q_2 = G_v Q_1 drift by about
+ * u32 kappa(A)); finished columns of Q~ then keep the row-checksum relation to
+ * FP64 rounding, while unfinished columns and the R checksum columns hold it to
+ * FP32 rounding of the updates.  CQR_TRAIL_BF16X3 is reserved. */
 typedef enum { CQR_FP64 = 0, CQR_TRAIL_FP32 = 1, CQR_TRAIL_BF16X3 = 2 } cqr_precision;
 
 typedef struct {
@@ -81,8 +91,8 @@ typedef struct cqr_plan_s* cqr_plan;
  *     Systematic MDS construction).  Ignored if K_h = 0.
  *   Requires: K_v <= p_r/2 when K_v > 0 (post-orthogonalization construction);
  *   m % p_r == n % p_c == n % p_r == 0; b | n; p_r, p_c <= 32; K_v, K_h <= 8;
- *   p_r + K_v <= 32 and p_c + K_h <= 32; precision == CQR_FP64 (the other
- *   values are reserved).
+ *   p_r + K_v <= 32 and p_c + K_h <= 32; precision is CQR_FP64 or
+ *   CQR_TRAIL_FP32.
  * Returns CQR_EINVAL on any violated condition; *out is then NULL.
  */
 cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, const double* gh,
@@ -186,11 +196,12 @@ cqr_status coded_qr_postorth(cqr_plan plan, const double* Q, int64_t ldq, double
  * inverse, 5 panel transform (P <- P R^{-1}), 6 in-panel projection (split
  * panels), 7 trailing product (R_bar = Qbar^T Q_t), 8 trailing update
  * (Q_t -= Qbar R_bar), 9 reduction of split-product partial tiles, 10 recovery,
- * 11 post-orthogonalization, 12 erase, 13 other (workspace/R initialisation).
+ * 11 post-orthogonalization, 12 erase, 13 other (workspace/R initialisation),
+ * 14 per-panel checksum re-encode (CQR_TRAIL_FP32 only).
  * coded_qr_profile_read returns, for `phase`, the summed event time (ms), the
  * number of launches and the summed flops / bytes (host outputs; may be NULL).
  */
-#define CQR_NPHASES 14
+#define CQR_NPHASES 15
 cqr_status coded_qr_profile_enable(cqr_plan plan, int32_t enable);
 cqr_status coded_qr_profile_read(cqr_plan plan, int32_t phase, double* total_ms, int64_t* launches,
                                  double* flops, double* bytes);

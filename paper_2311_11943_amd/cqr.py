@@ -29,7 +29,7 @@ EXPORTS = [
 
 PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram", "panel_chol", "panel_transform",
           "inpanel_projection", "trailing_product", "trailing_update", "split_reduce", "recover", "postorth",
-          "erase", "other"]
+          "erase", "other", "panel_reencode"]
 
 
 class CqrError(RuntimeError):

@@ -43,8 +43,8 @@ struct cqr_plan_s {
 };
 
 enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_CHOL, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
-             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER };
-static_assert(PH_OTHER + 1 == CQR_NPHASES, "phase list and header disagree");
+             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_REENCODE };
+static_assert(PH_REENCODE + 1 == CQR_NPHASES, "phase list and header disagree");
 
 namespace {
 
@@ -299,9 +299,9 @@ double partial_bytes(int nsplit, int ntiles) { return 8.0 * nsplit * ntiles * cq
 
 void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N,
         int64_t K, double* C, int64_t ldc, double* C2, int64_t ldc2, const cqr::Scratch& s, hipStream_t st,
-        int M2 = -1) {
+        int M2 = -1, bool f32 = false) {
   if (M <= 0 || N <= 0) return;
-  cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s);
+  cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s, 0, f32);
   if (M2 >= 0) a.M2 = M2;
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N);
   const double out = 8.0 * (double)M * N * (C2 ? 3.0 : 1.0);
@@ -316,9 +316,9 @@ void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B,
 }
 
 void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64_t lda, const double* B,
-        int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st) {
+        int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st, bool f32 = false) {
   if (M <= 0 || N <= 0 || K <= 0) return;
-  const cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s);
+  const cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, f32);
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)M * K + (double)K * N);
   const double upd = 16.0 * (double)M * N;
   const int tag = tag_of(phase);
@@ -406,7 +406,7 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   if (c.kv > 0 && 2 * c.kv > c.pr) return CQR_EINVAL;        // post-orthogonalization needs K_v <= p_r/2
   if (c.kh > c.pc && c.storage == CQR_IN_NODE) return CQR_EINVAL;
   if (c.storage != CQR_OUT_OF_NODE && c.storage != CQR_IN_NODE) return CQR_EINVAL;
-  if (c.precision != CQR_FP64) return CQR_EINVAL;
+  if (c.precision != CQR_FP64 && c.precision != CQR_TRAIL_FP32) return CQR_EINVAL;
   if (c.lookahead != 0 && c.lookahead != 1) return CQR_EINVAL;
   if (c.kv > 0 && !v_tilde) return CQR_EINVAL;
   if (c.kh > 0 && !gh) return CQR_EINVAL;
@@ -562,12 +562,30 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     if (e != hipSuccess) return hip_fail(e);
     st = p->chain;
   }
+  // the trailing-update products in FP32 (mixed precision) or FP64
+  const bool f32 = p->cfg.precision == CQR_TRAIL_FP32;
+  // With FP32 updates the systematic and checksum rows of a column are
+  // rounded independently, so Q_2 = G_v Q_1 drifts by the FP32 rounding of
+  // every update.  Relative to a column's final norm that drift grows like
+  // u32 kappa(A), and decoding would carry it into recovered blocks.  Each
+  // panel's checksum rows are therefore re-derived from its systematic rows in
+  // FP64 just before the panel is factored; the panel factorization is a
+  // column operation, so finished columns keep the relation to FP64 rounding.
+  cqr::EncodeArgs renc{};
+  const bool reencode = f32 && p->cfg.kv > 0;
+  if (reencode) {
+    renc.ld = ldq;
+    renc.m = p->cfg.m; renc.n = b; renc.bs = p->bs; renc.bw = p->bw;
+    renc.pr = p->cfg.pr; renc.pc = p->cfg.pc; renc.kv = p->cfg.kv; renc.kh = 0;
+    for (size_t e = 0; e < p->gv.size(); ++e) renc.g[e] = p->gv[e];
+  }
   // Panel k's update of columns [from, to):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
   auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
     double* Rb = R + c0 + from * ldr;
     const double* P = Q + c0 * ldq;
-    tn(*p, PH_TRAIL_TN, P, ldq, Q + from * ldq, ldq, (int)b, (int)(to - from), mp, Rb, ldr, nullptr, 0, sc, ss);
-    nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss);
+    tn(*p, PH_TRAIL_TN, P, ldq, Q + from * ldq, ldq, (int)b, (int)(to - from), mp, Rb, ldr, nullptr, 0, sc, ss, -1,
+       f32);
+    nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss, f32);
   };
   bool side_pending = false;
   // the caller's stream waits for the side stream's update of panel k-1
@@ -590,6 +608,12 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     const int64_t c0 = (int64_t)k * b, c1 = c0 + b;
     double* P = Q + c0 * ldq;
     const bool next = la && k + 1 < pe;     // panel k+1 is factored in this call
+    if (reencode) {
+      renc.At = P;
+      const double c = (double)renc.kv * renc.bs;
+      prof(*p, PH_REENCODE, 2.0 * c * renc.pr * b, 8.0 * (renc.m + c) * b, st,
+           [&] { cqr::launch_encode_rows(renc, st); });
+    }
     if (b <= kLeaf) {
       // First Cholesky-QR pass.  With re-projection its Gram matrix comes from
       // the same product as the coefficients, [Q[:, :c0] | P]^T P: since the
@@ -620,7 +644,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       apply(*p, P, ldq, (int)b, s, st);
       if (next) {
         // Q_next -= P R[panel, next]; the remaining columns on the side stream
-        nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st);
+        nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st, f32);
         if (c1 + b < N)
           if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
       } else if (c1 < N) {

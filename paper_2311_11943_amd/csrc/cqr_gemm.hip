@@ -25,9 +25,26 @@ namespace cqr {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ v4d mfma(double x, double y, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
 }
+
+// FP32 product of FP64 operands rounded to FP32, FP32 accumulation (the
+// mixed-precision trailing update).  Operand lanes as in the FP64 form.
+__device__ __forceinline__ v4f mfma(double x, double y, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32((float)x, (float)y, c, 0, 0, 0);
+}
+
+// Result layout of the transposed-issue 16x16x4 products: lane (li, g),
+// register r holds C[i0 + li][j0 + colsub(r, g)] -- the FP64 form spreads a
+// lane's four values over columns g, g+4, g+8, g+12, the FP32 form over the
+// consecutive columns 4g .. 4g+3.
+__device__ __forceinline__ int colsub(int r, int g, bool f32) { return f32 ? 4 * g + r : 4 * r + g; }
+
+template <bool F32> struct AccT { typedef v4d type; };
+template <> struct AccT<true> { typedef v4f type; };
 
 // Partial-tile layout shared by the product and reduction kernels: tile
 // `tile` of split `sp`, wave w, accumulator element q (16 per lane), lane l at
@@ -76,13 +93,14 @@ constexpr int LDP = KC + 2;      // padded LDS column (doubles)
 // row i0 + 16x + li, column j0 + 16y + 4r + g) to C, and add it into C2 if
 // given; the C2 loads are all issued before any store.
 __device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C2, int64_t ldc2, int M, int M2,
-                                               int N, int i0, int j0, int li, int g, const double (&v)[16]) {
+                                               int N, int i0, int j0, int li, int g, bool f32,
+                                               const double (&v)[16]) {
   double old[16];
   if (C2) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
-      const int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
+      const int i = i0 + 16 * x + li, j = j0 + 16 * y + colsub(r, g, f32);
       old[e] = (i < M2 && j < N) ? C2[i + (int64_t)j * ldc2] : 0.0;
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -90,7 +108,7 @@ __device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
-    const int i = i0 + 16 * x + li, j = j0 + 16 * y + 4 * r + g;
+    const int i = i0 + 16 * x + li, j = j0 + 16 * y + colsub(r, g, f32);
     if (i < M && j < N) {
       C[i + (int64_t)j * ldc] = v[e];
       if (C2 && i < M2) C2[i + (int64_t)j * ldc2] = old[e] + v[e];
@@ -98,7 +116,8 @@ __device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C
   }
 }
 
-__device__ __forceinline__ void tn_store(const TnArgs& a, const v4d (&acc)[2][2], int tile, int split, int wave,
+template <class Acc>
+__device__ __forceinline__ void tn_store(const TnArgs& a, const Acc (&acc)[2][2], int tile, int split, int wave,
                                          int lane, int i0, int j0) {
   const int li = lane & 15, g = lane >> 4;
   if (a.nsplit > 1) {
@@ -114,11 +133,12 @@ __device__ __forceinline__ void tn_store(const TnArgs& a, const v4d (&acc)[2][2]
   double v[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = acc[e >> 3][(e >> 2) & 1][e & 3];
-  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.M2, a.N, i0, j0, li, g, v);
+  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.M2, a.N, i0, j0, li, g, sizeof(acc[0][0][0]) == 4, v);
 }
 
-template <int TAG>
+template <int TAG, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void tn_lds_kernel(TnArgs a) {
+  typedef typename AccT<F32>::type Acc;
   __shared__ double sA[2][64 * LDP];
   __shared__ double sB[2][64 * LDP];
   const int tile = blockIdx.x, split = blockIdx.y;
@@ -137,11 +157,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     ga[r] = a.A + (int64_t)(ia < a.M ? ia : 0) * a.lda + 2 * lq;
     gb[r] = a.B + (int64_t)(jb < a.N ? jb : 0) * a.ldb + 2 * lq;
   }
-  v4d acc[2][2];
+  Acc acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+    for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
   const int ia0 = (wave & 1) * 32, jb0 = (wave >> 1) * 32;
   const int nfull = (int)((ke - kb) / KC);
 
@@ -295,12 +315,12 @@ __global__ __launch_bounds__(256) void tn_reduce_kernel(TnArgs a) {
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
   const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int i = tm * 64 + (wave & 1) * 32 + 16 * (qg >> 1) + li;
-  const int j0 = tn * 64 + (wave >> 1) * 32 + 16 * (qg & 1) + g;     // column of u = 0; u adds 4u
+  const int jq = tn * 64 + (wave >> 1) * 32 + 16 * (qg & 1);         // + colsub(u, g)
   double old[4];
   if (a.C2) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int j = j0 + 4 * u;
+      const int j = jq + colsub(u, g, a.f32);
       old[u] = (i < a.M2 && j < a.N) ? a.C2[i + (int64_t)j * a.ldc2] : 0.0;
     }
   }
@@ -309,7 +329,7 @@ __global__ __launch_bounds__(256) void tn_reduce_kernel(TnArgs a) {
   if (i >= a.M) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int j = j0 + 4 * u;
+    const int j = jq + colsub(u, g, a.f32);
     if (j < a.N) {
       a.C[i + (int64_t)j * a.ldc] = v[u];
       if (a.C2 && i < a.M2) a.C2[i + (int64_t)j * a.ldc2] = old[u] + v[u];
@@ -331,7 +351,7 @@ static int pick_split(int tiles, int64_t K, int64_t cap) {
 }
 
 TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
-                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split) {
+                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split, bool f32) {
   TnArgs a{};
   a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
   a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2; a.M2 = M;
@@ -345,6 +365,7 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   a.M = M; a.N = N; a.K = K; a.kchunk = kchunk; a.nsplit = ns; a.tilesN = tilesN; a.ntiles = tiles;
   a.part = s.part;
   a.vec = aligned16(A, lda) && aligned16(B, ldb);
+  a.f32 = f32 && a.vec;     // the FP32 form exists for the LDS-staged kernel
   return a;
 }
 
@@ -355,10 +376,14 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
     hipLaunchKernelGGL(tn_direct_kernel, grid, dim3(256), 0, st, a);
     return;
   }
+  if (a.f32) {
+    hipLaunchKernelGGL((tn_lds_kernel<TAG_TRAIL, true>), grid, dim3(256), 0, st, a);
+    return;
+  }
   switch (tag) {
-    case TAG_TRAIL: hipLaunchKernelGGL(tn_lds_kernel<TAG_TRAIL>, grid, dim3(256), 0, st, a); break;
-    case TAG_REPROJ: hipLaunchKernelGGL(tn_lds_kernel<TAG_REPROJ>, grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL(tn_lds_kernel<TAG_PANEL>, grid, dim3(256), 0, st, a); break;
+    case TAG_TRAIL: hipLaunchKernelGGL((tn_lds_kernel<TAG_TRAIL, false>), grid, dim3(256), 0, st, a); break;
+    case TAG_REPROJ: hipLaunchKernelGGL((tn_lds_kernel<TAG_REPROJ, false>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((tn_lds_kernel<TAG_PANEL, false>), grid, dim3(256), 0, st, a); break;
   }
 }
 
@@ -756,7 +781,8 @@ __device__ __forceinline__ void nn_load_tail(const NnArgs& a, const NnTile& t, i
   for (int e = 0; e < 16; ++e) sBb[kq + e][j] = (k0 + kq + e < ke) ? t.bp[k0 + e] : 0.0;
 }
 
-__device__ __forceinline__ void nn_mma(v4d (&acc)[4], const double (*sBb)[64 + 1], const NnTile& t,
+template <class Acc>
+__device__ __forceinline__ void nn_mma(Acc (&acc)[4], const double (*sBb)[64 + 1], const NnTile& t,
                                        const double (&xa)[16]) {
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
@@ -768,14 +794,15 @@ __device__ __forceinline__ void nn_mma(v4d (&acc)[4], const double (*sBb)[64 + 1
 
 // C -= A B for K <= 64 (the trailing update: K = b): every load of the tile
 // (C, A, the B slab) is issued before the first product.
-template <int TAG>
+template <int TAG, bool F32>
 __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
+  typedef typename AccT<F32>::type Acc;
   __shared__ double sB[NK][64 + 1];
   const NnTile t = nn_tile(a, blockIdx.x);
   double cval[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    const int j = t.jb + 16 * (e >> 2) + 4 * (e & 3) + t.g;
+    const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
     cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
   }
   double xa[16];
@@ -789,16 +816,16 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
     nn_load_tail(a, t, 0, a.K, xa, sB);
   }
   __syncthreads();
-  v4d acc[4];
+  Acc acc[4];
 #pragma unroll
-  for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
+  for (int y = 0; y < 4; ++y) acc[y] = Acc{0, 0, 0, 0};
   nn_mma(acc, sB, t, xa);
   if (!t.aok) return;
 #pragma unroll
   for (int y = 0; y < 4; ++y)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j = t.jb + 16 * y + 4 * r + t.g;
+      const int j = t.jb + 16 * y + colsub(r, t.g, F32);
       if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
     }
 }
@@ -807,17 +834,18 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
 // current slab is multiplied (A register sets alternate explicitly).  SPLIT:
 // the block's K range is one split and its partial tile is stored for
 // nn_reduce_kernel; otherwise C is read at the end and updated in place.
-template <bool SPLIT, int TAG>
+template <bool SPLIT, int TAG, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_kernel(NnArgs a) {
+  typedef typename AccT<F32>::type Acc;
   __shared__ double sB[2][NK][64 + 1];
   const int split = blockIdx.y;
   const NnTile t = nn_tile(a, blockIdx.x);
   const int kb = split * a.kchunk;
   const int ke = std::min(a.K, kb + a.kchunk);
   const int nfull = a.vec ? (ke - kb) / NK : 0;
-  v4d acc[4];
+  Acc acc[4];
 #pragma unroll
-  for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
+  for (int y = 0; y < 4; ++y) acc[y] = Acc{0, 0, 0, 0};
   auto koff = [&](int sl) { return kb + std::min(sl, nfull - 1) * NK; };
   if (nfull > 0) {
     double xa0[16], xa1[16];
@@ -867,7 +895,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   double cval[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    const int j = t.jb + 16 * (e >> 2) + 4 * (e & 3) + t.g;
+    const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
     cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
   }
   if (!t.aok) return;
@@ -875,7 +903,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   for (int y = 0; y < 4; ++y)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j = t.jb + 16 * y + 4 * r + t.g;
+      const int j = t.jb + 16 * y + colsub(r, t.g, F32);
       if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
     }
 }
@@ -887,13 +915,13 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
   const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int64_t i = (int64_t)tm * 64 + wave * 16 + li;
-  const int j0 = tn * 64 + 16 * qg + g;
+  const int jq = tn * 64 + 16 * qg;            // + colsub(u, g)
   const bool aok = i < a.M;
   const int64_t ic = aok ? i : 0;
   double old[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int j = j0 + 4 * u;
+    const int j = jq + colsub(u, g, a.f32);
     old[u] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
   }
   double v[4];
@@ -901,14 +929,15 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
   if (!aok) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int j = j0 + 4 * u;
+    const int j = jq + colsub(u, g, a.f32);
     if (j < a.N) a.C[i + (int64_t)j * a.ldc] = old[u] - v[u];
   }
 }
 
 NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
-                int N, int K, const Scratch& s) {
+                int N, int K, const Scratch& s, bool f32) {
   NnArgs a{};
+  a.f32 = f32;
   a.C = C; a.ldc = ldc; a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
   a.M = M; a.N = N; a.K = K;
   a.tilesN = (N + 63) / 64;
@@ -930,22 +959,26 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
   return a;
 }
 
-template <int TAG>
+template <int TAG, bool F32>
 static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
   if (a.K <= NK)
-    hipLaunchKernelGGL(nn1_kernel<TAG>, dim3(a.ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nn1_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (a.nsplit > 1)
-    hipLaunchKernelGGL((nn_kernel<true, TAG>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nn_kernel<true, TAG, F32>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((nn_kernel<false, TAG>), dim3(a.ntiles, 1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nn_kernel<false, TAG, F32>), dim3(a.ntiles, 1), dim3(256), 0, st, a);
 }
 
 void launch_nn_product(const NnArgs& a, int tag, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.K <= 0) return;
+  if (a.f32) {
+    nn_launch_tag<TAG_TRAIL, true>(a, st);
+    return;
+  }
   switch (tag) {
-    case TAG_TRAIL: nn_launch_tag<TAG_TRAIL>(a, st); break;
-    case TAG_REPROJ: nn_launch_tag<TAG_REPROJ>(a, st); break;
-    default: nn_launch_tag<TAG_PANEL>(a, st); break;
+    case TAG_TRAIL: nn_launch_tag<TAG_TRAIL, false>(a, st); break;
+    case TAG_REPROJ: nn_launch_tag<TAG_REPROJ, false>(a, st); break;
+    default: nn_launch_tag<TAG_PANEL, false>(a, st); break;
   }
 }
 

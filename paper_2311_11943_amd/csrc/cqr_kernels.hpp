@@ -76,13 +76,16 @@ struct TnArgs {
   int M2;             // only rows i < M2 are added into C2
   double* part;
   int vec;            // both operands 16-byte aligned with even leading dimensions
+  int f32;            // FP32 products (operands rounded), FP32 accumulation
 };
 
 // Choose the split of C = A^T B (stored to C; rows below M2 -- all rows
 // unless changed -- also added into C2 if C2 != nullptr).
 // force_split > 0 fixes the split count (capped by the partial capacity).
+// f32: the product in FP32 (operands rounded to FP32, FP32 accumulation), for
+// the mixed-precision trailing update.
 TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
-                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0);
+                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0, bool f32 = false);
 // The product; with nsplit == 1 it stores C (and C2) itself, else partials.
 void launch_tn_product(const TnArgs& a, int tag, hipStream_t st);
 // Sum the partials into C (and C2) in split order (nsplit > 1 only).
@@ -96,10 +99,11 @@ struct NnArgs {
   int64_t M; int N; int K;
   int kchunk; int nsplit; int tilesN; int ntiles;
   int vec;            // B 16-byte aligned with even ldb (vector B loads)
+  int f32;            // FP32 products (operands rounded), FP32 accumulation
   double* part;
 };
 NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
-                int N, int K, const Scratch& s);
+                int N, int K, const Scratch& s, bool f32 = false);
 void launch_nn_product(const NnArgs& a, int tag, hipStream_t st);
 void launch_nn_reduce(const NnArgs& a, hipStream_t st);   // nsplit > 1 only
 

@@ -88,6 +88,7 @@ def test_plan_generators_and_tolerance_match_oracle(pr, pc, kv, kh, storage):
     dict(kv=9),                     # too many checksums
     dict(kv=3),                     # post-orthogonalization needs K_v <= p_r / 2
     dict(precision=7),              # unknown precision
+    dict(precision=2),              # reserved precision
     dict(storage=5),                # unknown storage
 ])
 def test_plan_create_rejects_invalid_configs(bad):
@@ -99,6 +100,12 @@ def test_plan_create_rejects_invalid_configs(bad):
                                  if cfg.kv <= 8 and cfg.pr > cfg.kv else None,
                                  synth.r_generator_draws(cfg.pc, cfg.kh, 1))
     assert e.value.status == cqr.CQR_EINVAL
+
+
+def test_plan_accepts_fp32_trailing_precision():
+    cfg = cqr.Config(m=256, n=256, pr=4, pc=4, kv=1, kh=1, b=16, precision=cqr.CQR_TRAIL_FP32)
+    p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(1, 4, 1), synth.r_generator_draws(4, 1, 1))
+    cqr.coded_qr_plan_destroy(p)
 
 
 def test_oracle_not_imported_by_product_package():
