@@ -263,6 +263,16 @@ def main():
         t_enc = timed(enc)
         t_fac = timed(lambda: (enc(), fac()))  - t_enc
         t_post = timed(lambda: q.postorth(At, Qpost, B, Bpost))
+        # coded solve R_1 x = (G_0 Q_1)^T (G_0 b) on the last step's factors
+        X = cqr.col_major(n, 1, dev)
+        ws_solve = q.solve_workspace(1)
+
+        def solve():
+            q.solve(Qpost, R, Bpost, X, ws_solve)
+        t_solve = timed(solve)
+        x_direct = torch.linalg.solve(A, B)
+        out["solve"] = {"ms": round(t_solve, 4),
+                        "rel_err_vs_direct": (torch.linalg.norm(X - x_direct) / torch.linalg.norm(x_direct)).item()}
         # uncoded: same library, K = 0
         cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead, precision=prec)
         qu = cqr.CodedQR(cu, None, None, dev)

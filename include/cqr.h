@@ -184,6 +184,29 @@ cqr_status coded_qr_postorth(cqr_plan plan, const double* Q, int64_t ldq, double
                              hipStream_t stream);
 
 /*
+ * Coded linear solve (the linear-solve equations that follow the theorem on
+ * low-cost post-orthogonalization):  R_1 X = Qpost^T Bpost, i.e.
+ *   X = R_1^{-1} (G_0 Q_1)^T (G_0 B),
+ * with Qpost = G_0 Q_1 and Bpost = G_0 B from coded_qr_postorth and R_1 =
+ * R[0:n, 0:n] from coded_qr_factor.  For square A this is the solution of
+ * A X = B.  For tall A (m > n) it minimises (AX - B)^T W (AX - B) with
+ * W = I + G_v^T G_v (ordinary least squares only when the residual is zero).
+ * Qpost (device, m x n, ldqp >= m), R (device, ldr >= n; only its upper
+ * triangle R[0:n, 0:n] is read), Bpost (device, m x nrhs, ldbp >= m),
+ * X (device, n x nrhs, ldx >= n, written; must not alias the inputs).
+ * nrhs >= 1.  ws: caller-owned device workspace, 256-byte aligned, of at least
+ * coded_qr_solve_workspace_bytes(plan, nrhs) bytes (the inverted 64 x 64
+ * diagonal blocks of R_1 and Y = Qpost^T Bpost); CQR_ENOMEM if smaller or
+ * misaligned.  No pivoting and no singularity check: R_1 from coded_qr_factor
+ * has a positive diagonal whenever its info is 0, and a zero pivot gives
+ * non-finite entries of X.
+ */
+size_t coded_qr_solve_workspace_bytes(cqr_plan plan, int32_t nrhs);
+cqr_status coded_qr_solve(cqr_plan plan, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
+                          const double* Bpost, int64_t ldbp, int32_t nrhs, double* X, int64_t ldx, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
+/*
  * Per-phase timing (diagnostics).  While enabled, the plan records a HIP event
  * pair around every kernel launch, on the stream that launch runs on, and
  * remembers the phase, the algorithmic flops and the minimum HBM bytes of that
@@ -197,11 +220,11 @@ cqr_status coded_qr_postorth(cqr_plan plan, const double* Q, int64_t ldq, double
  * panels), 7 trailing product (R_bar = Qbar^T Q_t), 8 trailing update
  * (Q_t -= Qbar R_bar), 9 reduction of split-product partial tiles, 10 recovery,
  * 11 post-orthogonalization, 12 erase, 13 other (workspace/R initialisation),
- * 14 per-panel checksum re-encode (CQR_TRAIL_FP32 only).
+ * 14 per-panel checksum re-encode (CQR_TRAIL_FP32 only), 15 coded solve.
  * coded_qr_profile_read returns, for `phase`, the summed event time (ms), the
  * number of launches and the summed flops / bytes (host outputs; may be NULL).
  */
-#define CQR_NPHASES 15
+#define CQR_NPHASES 16
 cqr_status coded_qr_profile_enable(cqr_plan plan, int32_t enable);
 cqr_status coded_qr_profile_read(cqr_plan plan, int32_t phase, double* total_ms, int64_t* launches,
                                  double* flops, double* bytes);

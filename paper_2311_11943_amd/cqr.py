@@ -24,12 +24,13 @@ EXPORTS = [
     "coded_qr_plan_create", "coded_qr_plan_destroy", "coded_qr_plan_generators", "coded_qr_plan_ftol",
     "coded_qr_workspace_bytes", "coded_qr_encode", "coded_qr_factor", "coded_qr_ws_info",
     "coded_qr_erase", "coded_qr_recover", "coded_qr_postorth", "coded_qr_status_string",
-    "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name",
+    "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name", "coded_qr_solve",
+    "coded_qr_solve_workspace_bytes",
 ]
 
 PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram", "panel_chol", "panel_transform",
           "inpanel_projection", "trailing_product", "trailing_update", "split_reduce", "recover", "postorth",
-          "erase", "other", "panel_reencode"]
+          "erase", "other", "panel_reencode", "solve"]
 
 
 class CqrError(RuntimeError):
@@ -70,6 +71,8 @@ def _load() -> ctypes.CDLL:
         "coded_qr_erase": (I32, [P, D, I64, D, I64, P, I32, V]),
         "coded_qr_recover": (I32, [P, D, I64, D, I64, P, I32, V]),
         "coded_qr_postorth": (I32, [P, D, I64, D, I64, D, I64, D, I64, I32, V]),
+        "coded_qr_solve": (I32, [P, D, I64, D, I64, D, I64, I32, D, I64, V, ctypes.c_size_t, V]),
+        "coded_qr_solve_workspace_bytes": (ctypes.c_size_t, [P, I32]),
         "coded_qr_status_string": (ctypes.c_char_p, [I32]),
         "coded_qr_hip_error_name": (ctypes.c_char_p, []),
         "coded_qr_profile_enable": (I32, [P, I32]),
@@ -251,6 +254,17 @@ def coded_qr_postorth(plan: int, Q, Qpost, B=None, Bpost=None, stream=None) -> i
                                  ctypes.c_void_p(_stream(stream)))
 
 
+def coded_qr_solve_workspace_bytes(plan: int, nrhs: int) -> int:
+    return LIB.coded_qr_solve_workspace_bytes(ctypes.c_void_p(plan), nrhs)
+
+
+def coded_qr_solve(plan: int, Qpost, R, Bpost, X, ws, stream=None) -> int:
+    """ws: device tensor of at least coded_qr_solve_workspace_bytes(plan, nrhs) bytes."""
+    return LIB.coded_qr_solve(ctypes.c_void_p(plan), _ptr(Qpost), _ld(Qpost), _ptr(R), _ld(R), _ptr(Bpost),
+                              _ld(Bpost), Bpost.shape[1], _ptr(X), _ld(X), _ptr(ws),
+                              ws.numel() * ws.element_size(), ctypes.c_void_p(_stream(stream)))
+
+
 def coded_qr_profile_enable(plan: int, enable: bool) -> int:
     return LIB.coded_qr_profile_enable(ctypes.c_void_p(plan), int(bool(enable)))
 
@@ -325,6 +339,19 @@ class CodedQR:
 
     def postorth(self, Q, Qpost, B=None, Bpost=None):
         _check(coded_qr_postorth(self.plan, Q, Qpost, B, Bpost), "coded_qr_postorth")
+
+    def solve_workspace(self, nrhs: int):
+        import torch
+        nbytes = coded_qr_solve_workspace_bytes(self.plan, nrhs)
+        return torch.empty(((nbytes + 7) // 8,), dtype=torch.float64, device=self.device)
+
+    def solve(self, Qpost, R, Bpost, X=None, ws=None):
+        """X = R_1^{-1} Qpost^T Bpost (n x nrhs, column-major, on the device)."""
+        nrhs = Bpost.shape[1]
+        X = col_major(self.cfg.n, nrhs, self.device) if X is None else X
+        ws = self.solve_workspace(nrhs) if ws is None else ws
+        _check(coded_qr_solve(self.plan, Qpost, R, Bpost, X, ws), "coded_qr_solve")
+        return X
 
     def run(self, A_dev, schedule=(), B=None):
         """encode -> factor with scheduled erasures/recoveries -> post-orth.

@@ -43,8 +43,8 @@ struct cqr_plan_s {
 };
 
 enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_CHOL, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
-             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_REENCODE };
-static_assert(PH_REENCODE + 1 == CQR_NPHASES, "phase list and header disagree");
+             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_REENCODE, PH_SOLVE };
+static_assert(PH_SOLVE + 1 == CQR_NPHASES, "phase list and header disagree");
 
 namespace {
 
@@ -815,6 +815,39 @@ cqr_status coded_qr_postorth(cqr_plan p, const double* Q, int64_t ldq, double* Q
   if (nrhs > 0) {
     a.src = B; a.lds = ldb; a.dst = Bpost; a.ldd = ldbp; a.cols = nrhs;
     prof(*p, PH_POST, fl_el * m * nrhs, 16.0 * m * nrhs, st, [&] { cqr::launch_postorth(a, st); });
+  }
+  return hip_status();
+}
+
+size_t coded_qr_solve_workspace_bytes(cqr_plan p, int32_t nrhs) {
+  if (!p || nrhs < 1) return 0;
+  const int64_t n = p->cfg.n, nb = (n + 63) / 64;
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return up(8 * (size_t)nb * 64 * 64) + up(8 * (size_t)n * nrhs);
+}
+
+cqr_status coded_qr_solve(cqr_plan p, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
+                          const double* Bpost, int64_t ldbp, int32_t nrhs, double* X, int64_t ldx, void* ws,
+                          size_t ws_bytes, hipStream_t st) {
+  drop_pending_error();
+  if (!p || !Qpost || !R || !Bpost || !X || !ws || nrhs < 1) return CQR_EINVAL;
+  const int64_t m = p->cfg.m, n = p->cfg.n, nb = (n + 63) / 64;
+  if (ldqp < m || ldr < n || ldbp < m || ldx < n) return CQR_EINVAL;
+  if (ws_bytes < coded_qr_solve_workspace_bytes(p, nrhs) || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return CQR_ENOMEM;
+  double* T = static_cast<double*>(ws);
+  double* Y = T + ((8 * (size_t)nb * 64 * 64 + 255) & ~size_t(255)) / 8;
+  // inverses of the 64 x 64 diagonal blocks of R_1, all at once
+  prof(*p, PH_SOLVE, nb * 64.0 * 64 * 64 / 3, 8.0 * (n * 64.0 + nb * 64.0 * 64), st,
+       [&] { cqr::launch_trinv(R, ldr, n, T, st); });
+  // Y = Qpost^T Bpost
+  prof(*p, PH_SOLVE, 2.0 * m * n * nrhs, 8.0 * (m * n + m * nrhs + n * nrhs), st,
+       [&] { cqr::launch_gemv_t(Qpost, ldqp, m, (int)n, Bpost, ldbp, nrhs, Y, n, st); });
+  // R_1 X = Y, 64-row blocks from the bottom
+  for (int64_t k0 = (nb - 1) * 64; k0 >= 0; k0 -= 64) {
+    const int w = (int)std::min<int64_t>(64, n - k0);
+    prof(*p, PH_SOLVE, 2.0 * (64.0 * w + k0 * w) * nrhs, 8.0 * (k0 * w + 64.0 * 64 + 2.0 * (k0 + w) * nrhs), st,
+         [&] { cqr::launch_trsv_step(R, ldr, T, Y, n, X, ldx, nrhs, k0, w, st); });
   }
   return hip_status();
 }

@@ -124,5 +124,11 @@ void launch_encode_cols(const EncodeArgs& a, hipStream_t st);
 void launch_line(const LineArgs& a, hipStream_t st);
 void launch_erase(const EraseArgs& a, hipStream_t st);
 void launch_postorth(const PostArgs& a, hipStream_t st);
+// coded solve: Y = Q^T B (Q m x n), then blocked back substitution with R_1
+void launch_gemv_t(const double* Q, int64_t ldq, int64_t m, int n, const double* B, int64_t ldb, int nrhs,
+                   double* Y, int64_t ldy, hipStream_t st);
+void launch_trinv(const double* R, int64_t ldr, int64_t n, double* T, hipStream_t st);
+void launch_trsv_step(const double* R, int64_t ldr, const double* T, double* Y, int64_t ldy, double* X,
+                      int64_t ldx, int nrhs, int64_t k0, int w, hipStream_t st);
 
 }  // namespace cqr

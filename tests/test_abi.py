@@ -108,6 +108,17 @@ def test_plan_accepts_fp32_trailing_precision():
     cqr.coded_qr_plan_destroy(p)
 
 
+def test_solve_workspace_size():
+    cfg = cqr.Config(m=240, n=240, pr=4, pc=4, kv=1, kh=1, b=16)
+    p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(1, 4, 1), synth.r_generator_draws(4, 1, 1))
+    try:
+        # four inverted 64 x 64 diagonal blocks, then Y (240 x nrhs), each 256-byte aligned
+        assert cqr.coded_qr_solve_workspace_bytes(p, 3) == 4 * 64 * 64 * 8 + 5888
+        assert cqr.coded_qr_solve_workspace_bytes(p, 0) == 0
+    finally:
+        cqr.coded_qr_plan_destroy(p)
+
+
 def test_oracle_not_imported_by_product_package():
     pkg = os.path.join(ROOT, "paper_2311_11943_amd")
     for dirpath, _, files in os.walk(pkg):

@@ -1,7 +1,8 @@
 """Full-size parity: the benchmark's workload (n = 4096 Gaussian, 8 x 8 grid,
 b = 64, K = 2 in-node checksums, two random single-node failures at random
 panels) run through the C ABI exactly as bench.py times it (lookahead on,
-same seeds, same schedule), against the FP64 oracle element by element.
+same seeds, same schedule), then the coded solve, against the FP64 oracle
+element by element.
 The oracle takes ~10 s on the host cores at this size."""
 import numpy as np
 import pytest
@@ -34,6 +35,7 @@ def test_bench_workload_matches_oracle():
                           cqr.to_device_colmajor(inp["rhs"], "cuda:0"))
     torch.cuda.synchronize()
     assert q.info() == 0
+    Xg = host(q.solve(Qp, R, Bp))
     Qg, Rg, Qpg, Bpg = host(At), host(R), host(Qp), host(Bp)
     q.close()
 
@@ -48,5 +50,7 @@ def test_bench_workload_matches_oracle():
     Qt = Qg[:, :n]
     orth = np.linalg.norm(np.eye(n) - Qt.T @ Qt)
     assert res < 1e-12 and orth < 1e-12, (res, orth)
-    x = oc.coded_solve(Qpg, Rg[:, :n], Bpg)
-    np.testing.assert_allclose(x, np.linalg.solve(A, inp["rhs"]), rtol=1e-8, atol=1e-9)
+    # coded solve on the GPU against the oracle's and the direct solution
+    xo = oc.coded_solve(ref["Qpost"], ref["R"][:, :n], ref["bpost"])
+    assert rel(Xg, xo) < 1e-9
+    np.testing.assert_allclose(Xg, np.linalg.solve(A, inp["rhs"]), rtol=1e-8, atol=1e-9)

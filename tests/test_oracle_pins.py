@@ -362,6 +362,26 @@ def test_pipeline_with_failures_equals_failure_free(storage, K):
     np.testing.assert_allclose(x, np.linalg.solve(A, rhs), rtol=1e-9, atol=1e-10)
 
 
+def test_tall_coded_solve_is_weighted_least_squares():
+    """For tall A the post-orthogonalized solve x = R_1^{-1} (G_0 Q_1)^T (G_0 b)
+    minimises (Ax - b)^T W (Ax - b) with W = I + G_v^T G_v: closed form
+    (A^T W A)^{-1} A^T W b.  With a nonzero residual this differs from
+    ordinary least squares."""
+    m, n, pr, K, b = 512, 64, 8, 2, 16
+    lay = oc.Layout(m, n, pr, 1, K, 0, oc.OUT_OF_NODE)
+    A = synth.gaussian(m, n, 5)
+    v = synth.q_generator_draws(K, pr, 5)
+    rhs = synth.gaussian(m, 3, 6)
+    out = oc.run(oc.Problem(A, lay, v, None, oc.FactorOptions(b, "cgs2"), [], rhs))
+    x = oc.coded_solve(out["Qpost"], out["R"][:, :n], out["bpost"])
+    Gv = np.kron(oc.q_generator(v), np.eye(lay.bs))
+    W = np.eye(m) + Gv.T @ Gv
+    xw = np.linalg.solve(A.T @ W @ A, A.T @ W @ rhs)
+    np.testing.assert_allclose(x, xw, rtol=1e-11, atol=1e-12)
+    xo = np.linalg.lstsq(A, rhs, rcond=None)[0]
+    assert np.abs(x - xo).max() > 1e-6
+
+
 # ---------------------------------------------------------------- planted mistakes
 def test_pins_catch_planted_mistakes(monkeypatch):
     """A wrong sign in the generator construction breaks the post-orth
