@@ -57,12 +57,14 @@ SINGLE_KERNEL_PHASES = ("trailing_product", "trailing_update", "reproj_product",
                         "recover", "postorth")
 KERNEL_OF = {
     "encode": "encode_rows_kernel / encode_cols_kernel",
-    "reproj_product": "tn_lds_kernel<1>", "reproj_update": "nn_kernel<*, 1>", "panel_gram": "tn_lds_kernel<2>",
-    "panel_chol": "chol_kernel", "panel_transform": "apply_kernel", "inpanel_projection": "tn/nn <2>",
-    "trailing_product": "tn_lds_kernel<0>", "trailing_update": "nn1_kernel<0>",
-    "split_reduce": "tn_reduce_kernel / nn_reduce_kernel / gram_sum_kernel", "recover": "line_kernel",
+    "reproj_product": "tn_lds_kernel<1, false>", "reproj_update": "nn_kernel<*, 1, false>",
+    "panel_gram": "tn_lds_kernel<2, false>", "panel_chol": "chol_kernel", "panel_transform": "apply_kernel",
+    "inpanel_projection": "tn/nn <2, false>",
+    "trailing_product": "tn_lds_kernel<0, false>", "trailing_update": "nn1_kernel<0, false>",
+    "split_reduce": "tn_reduce_kernel / nn_reduce_kernel", "recover": "line_kernel",
     "postorth": "postorth_kernel", "erase": "erase_kernel", "other": "zero_ints_kernel / fill_zero_kernel",
     "panel_reencode": "encode_rows_kernel (one panel)",
+    "solve": "trinv_kernel / gemv_t_kernel / trsv_step_kernel",
 }
 
 
@@ -111,9 +113,10 @@ def conditioned_input(n: int, cond: float, seed: int, dev) -> np.ndarray:
 
 
 def source_hash() -> str:
+    """Hash of the sources the product kernels (the roofline candidates) are built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_11943_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("cqr_gemm.hip", "cqr_kernels.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -135,6 +138,90 @@ def traffic_record(phase: str, workload: str):
     return r.get("bytes_per_launch")
 
 
+def run_sweep(args):
+    """The paper's overhead experiments on one GPU (T_coding vs p and vs f;
+    T_enc and p T_recov vs f): n = 24000 Gaussian, p = p_r = p_c in
+    {6, 8, 10, 12}, f = K out-of-node checksums in {0, 1, 2, 3}, one panel per
+    grid block column (b = n/p, factored recursively in leaves of <= 64
+    columns), a reverse-diagonal failure of f nodes per grid row and column at
+    every panel boundary.  One JSON line per (p, f)."""
+    import torch
+    from paper_2311_11943_amd import cqr
+    dev = torch.device("cuda:0")
+    n = args.sweep_n
+    A_host = synth.gaussian(n, n, args.seed)
+    A = cqr.to_device_colmajor(A_host, dev)
+    del A_host
+
+    def ev_ms(fn):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        z.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(z)
+
+    for p in (6, 8, 10, 12):
+        b = n // p
+        # uncoded factorization time (same library, no checksums)
+        qu = cqr.CodedQR(cqr.Config(n, n, p, p, 0, 0, b, cqr.CQR_OUT_OF_NODE), None, None, dev)
+        Au, Ru = qu.alloc()
+        t_qr = []
+        for _ in range(2):
+            Au.copy_(A)
+            t_qr.append(ev_ms(lambda: qu.factor(Au, Ru)))
+        T_qr = t_qr[-1]
+        qu.close()
+        del Au, Ru
+        for f in (0, 1, 2, 3):
+            if f == 0:
+                print(json.dumps({"sweep": "coding overhead vs p and f", "n": n, "p": p, "f": 0, "b": b,
+                                  "T_QR_ms": round(T_qr, 3)}), flush=True)
+                continue
+            cfg = cqr.Config(n, n, p, p, f, f, b, cqr.CQR_OUT_OF_NODE)
+            q = cqr.CodedQR(cfg, synth.q_generator_draws(f, p, args.seed), synth.r_generator_draws(p, f, args.seed),
+                            dev)
+            At, R = q.alloc()
+            Qpost = cqr.col_major(n, n, dev)
+
+            def enc():
+                At[:n, :n].copy_(A)
+                q.encode(At)
+            enc()
+            t_copy = ev_ms(lambda: At[:n, :n].copy_(A))
+            T_enc = ev_ms(enc) - t_copy
+            T_fac = ev_ms(lambda: q.factor(At, R))
+            T_post = ev_ms(lambda: q.postorth(At, Qpost))
+            # the same factorization with a reverse-diagonal failure at every panel boundary
+            sched = synth.draw_schedule("revdiag", p, p, p, args.seed, every=1, f=f)
+            enc()
+            k, t_rec = 0, 0.0
+            for t, nodes in sched:
+                q.factor(At, R, k, t)
+                k = t
+                q.erase(At, R, nodes)
+                t_rec += ev_ms(lambda: q.recover(At, R, nodes))
+            q.factor(At, R, k, cfg.npanels)
+            torch.cuda.synchronize()
+            res = (torch.linalg.norm(A - At[:n, :n] @ R[:, :n]) / torch.linalg.norm(A)).item()
+            Qt = At[:, :n]
+            orth = torch.linalg.norm(torch.eye(n, device=dev, dtype=torch.float64) - Qt.T @ Qt).item()
+            T_rec = t_rec / max(len(sched), 1)
+            print(json.dumps({
+                "sweep": "coding overhead vs p and f", "n": n, "p": p, "f": f, "b": b,
+                "T_QR_ms": round(T_qr, 3), "T_enc_ms": round(T_enc, 3), "T_factor_coded_ms": round(T_fac, 3),
+                "T_post_ms": round(T_post, 3),
+                "T_coding_pct": round(100 * (T_enc + T_fac + T_post - T_qr) / T_qr, 2),
+                "floor_pct": round(100 * ((1 + f / p) ** 2 - 1), 2),
+                "T_recov_ms_per_event": round(T_rec, 3), "p_T_recov_ms": round(p * T_rec, 3),
+                "events": len(sched), "nodes_per_event": len(sched[0][1]) if sched else 0,
+                "errors_with_failures": {"residual": res, "orth_coded": orth, "info": q.info()},
+            }), flush=True)
+            q.close()
+            del At, R, Qpost, Qt
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,12 +241,21 @@ def main():
                          "instead of a Gaussian A")
     ap.add_argument("--lookahead", type=int, default=1, choices=(0, 1),
                     help="1: overlap the next panel with the trailing update on a second stream")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: the paper's coding-overhead grid (n = 24000, "
+                         "p in {6, 8, 10, 12}, f in {0..3}), one JSON line per point")
+    ap.add_argument("--sweep-n", type=int, default=24000)
+    ap.add_argument("--reps", type=int, default=5, help="repetitions of each timed extra (overhead legs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the coded-QR hot path here runs on a single MI355X "
               "(the processor grid is simulated as blocks of one matrix); --gpus must be 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        run_sweep(args)
+        return
 
     import torch
     from paper_2311_11943_amd import cqr
@@ -197,9 +293,13 @@ def main():
             q.recover(At, R, nodes)
         q.postorth(At, Qpost, B, Bpost)
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log(f"{args.warmup} warmup steps done")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
@@ -209,6 +309,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
+    log(f"{args.steps} timed steps done: {ms:.3f} ms per step")
     mp, d = cfg.mp, cfg.N - n
     F = model_flops(mp, n, d, b)
     value = F / (ms * 1e-3) / 1e12
@@ -242,7 +343,7 @@ def main():
     out["errors"] = {"residual": res, "orth_coded": orth, "orth_post": orth_p, "info": q.info()}
 
     if not args.no_extras:
-        def timed(fn, reps=5):
+        def timed(fn, reps=args.reps):
             fn()
             torch.cuda.synchronize()
             a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -293,6 +394,7 @@ def main():
             "useful_tflops": round(model_flops(n, n, 0, b) / (ms * 1e-3) / 1e12, 4),
         }
         qu.close()
+        log("overhead legs done")
 
         # profiled pass: per-kernel HIP events on the library's stream
         q.profile(True)
@@ -311,6 +413,11 @@ def main():
         out["overhead"]["T_recov_ms_per_event"] = round(rec_ms / max(len(sched), 1), 4)
         # the kernel holding the most time among phases that are exactly one
         # kernel symbol (so rocprofv3's per-kernel average describes the same launches)
+        def kernel_of(phase):
+            # the trailing products are the FP32 instances in the mixed form
+            k = KERNEL_OF[phase]
+            return k.replace("<0, false>", "<0, true>") if args.precision == "fp32" else k
+
         dom = max((k for k in SINGLE_KERNEL_PHASES if rep[k]["launches"]), key=lambda k: rep[k]["ms"])
         r = rep[dom]
         if dom in MFMA_PHASES:
@@ -318,16 +425,16 @@ def main():
             # the trailing products run on FP32 MFMA in the mixed form, everything else on FP64
             pk = PEAK["fp32_mfma_tflops" if args.precision == "fp32" and dom == "trailing_product"
                       else "fp64_mfma_tflops"]
-            roof = {"kernel": KERNEL_OF[dom], "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
+            roof = {"kernel": kernel_of(dom), "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
                     "peak": pk, "unit": "TFLOP/s", "frac": round(ach / pk, 4)}
         else:
             ach = r["bytes"] / (r["ms"] * 1e-3) / 1e9
-            roof = {"kernel": KERNEL_OF[dom], "phase": dom, "bound": "hbm", "achieved": round(ach, 1),
+            roof = {"kernel": kernel_of(dom), "phase": dom, "bound": "hbm", "achieved": round(ach, 1),
                     "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
         roof["avg_launch_us"] = round(1e3 * r["ms"] / r["launches"], 3)
         roof["launches"] = r["launches"]
         roof["share_of_profiled_step"] = round(r["ms"] / sum(x["ms"] for x in rep.values()), 3)
-        roof["traffic"] = traffic_record(dom, args.workload)
+        roof["traffic"] = traffic_record(dom, args.workload) if args.precision == "fp64" else None
         roof["events_per_step"] = 2 * nrec
         out["roofline"] = roof
 
