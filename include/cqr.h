@@ -207,6 +207,50 @@ cqr_status coded_qr_solve(cqr_plan plan, const double* Qpost, int64_t ldqp, cons
                           size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Adjoint (reverse-mode derivative) of the coded QR.  Not in the paper: a
+ * growth direction built on its definitions.  The coded QR maps A to the
+ * factors of the encoded systematic columns, A~ = [A; G_v A] = Q~ R_1 (System
+ * Model, encoding equation).  Given the cotangents dQ~ (m' x n) and dR_1
+ * (n x n; only its upper triangle is read), this computes the standard
+ * reverse-mode rule of the thin QR followed by the encoding's transpose:
+ *   M = R_1 dR_1^T - dQ~^T Q~,   dA~ = (dQ~ + Q~ copyltu(M)) R_1^{-T},
+ *   dA = dA~_top + G_v^T dA~_bottom,
+ * where copyltu(M) is the symmetric matrix that holds M's lower triangle.
+ * Q (device, m' x n, ldq >= m': Q~ from coded_qr_factor), R (device,
+ * ldr >= n: R_1 = R[0:n, 0:n], zero below the diagonal as coded_qr_factor
+ * leaves it), dQ (device, m' x n, lddq >= m'), dR (device, n x n,
+ * lddr >= n), dA (device, m x n, ldda >= m, written; must not alias inputs).
+ * ws: caller-owned device workspace of at least
+ * coded_qr_backward_workspace_bytes(plan) bytes, 256-byte aligned, else
+ * CQR_ENOMEM (split-product partials, R_1^{-1}, three n x n and two m' x n
+ * buffers).  Asynchronous on `stream`; allocates nothing.
+ */
+size_t coded_qr_backward_workspace_bytes(cqr_plan plan);
+cqr_status coded_qr_backward(cqr_plan plan, const double* Q, int64_t ldq, const double* R, int64_t ldr,
+                             const double* dQ, int64_t lddq, const double* dR, int64_t lddr, double* dA,
+                             int64_t ldda, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint of the coded solve X = R_1^{-1} (G_0 Q_1)^T (G_0 B) (coded_qr_solve).
+ * With dY = R_1^{-T} dX:
+ *   dR_1 = -triu(dY X^T),   dQ~[0:m] = G_0 (Bpost dY^T),   dQ~[m:m'] = 0,
+ *   dB = G_0 (Qpost dY)     (G_0 is symmetric, so it is its own transpose);
+ * dQ~ and dR_1 feed coded_qr_backward.  Qpost, Bpost from coded_qr_postorth
+ * (device, m x n and m x nrhs), R from coded_qr_factor, X from coded_qr_solve
+ * (device, n x nrhs, ldx >= n), dX (device, n x nrhs, lddx >= n).  Written:
+ * dQ (device, m' x n, lddq >= m'), dR (device, n x n upper, zero below,
+ * lddr >= n), dB (device, m x nrhs, lddb >= m).  Requires K_v > 0.  ws: at
+ * least coded_qr_solve_backward_workspace_bytes(plan, nrhs) bytes, 256-byte
+ * aligned, else CQR_ENOMEM.
+ */
+size_t coded_qr_solve_backward_workspace_bytes(cqr_plan plan, int32_t nrhs);
+cqr_status coded_qr_solve_backward(cqr_plan plan, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
+                                   const double* Bpost, int64_t ldbp, const double* X, int64_t ldx,
+                                   const double* dX, int64_t lddx, int32_t nrhs, double* dQ, int64_t lddq,
+                                   double* dR, int64_t lddr, double* dB, int64_t lddb, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/*
  * Per-phase timing (diagnostics).  While enabled, the plan records a HIP event
  * pair around every kernel launch, on the stream that launch runs on, and
  * remembers the phase, the algorithmic flops and the minimum HBM bytes of that
@@ -220,11 +264,12 @@ cqr_status coded_qr_solve(cqr_plan plan, const double* Qpost, int64_t ldqp, cons
  * panels), 7 trailing product (R_bar = Qbar^T Q_t), 8 trailing update
  * (Q_t -= Qbar R_bar), 9 reduction of split-product partial tiles, 10 recovery,
  * 11 post-orthogonalization, 12 erase, 13 other (workspace/R initialisation),
- * 14 per-panel checksum re-encode (CQR_TRAIL_FP32 only), 15 coded solve.
+ * 14 per-panel checksum re-encode (CQR_TRAIL_FP32 only), 15 coded solve,
+ * 16 adjoint (coded_qr_backward, coded_qr_solve_backward).
  * coded_qr_profile_read returns, for `phase`, the summed event time (ms), the
  * number of launches and the summed flops / bytes (host outputs; may be NULL).
  */
-#define CQR_NPHASES 16
+#define CQR_NPHASES 17
 cqr_status coded_qr_profile_enable(cqr_plan plan, int32_t enable);
 cqr_status coded_qr_profile_read(cqr_plan plan, int32_t phase, double* total_ms, int64_t* launches,
                                  double* flops, double* bytes);

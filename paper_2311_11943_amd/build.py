@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcqr.so")
 
-SOURCES = ["cqr_gemm.hip", "cqr_code.hip", "cqr_solve.hip", "cqr_api.cpp"]
+SOURCES = ["cqr_gemm.hip", "cqr_code.hip", "cqr_solve.hip", "cqr_adjoint.hip", "cqr_api.cpp"]
 ARCH = os.environ.get("CQR_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -25,12 +25,13 @@ EXPORTS = [
     "coded_qr_workspace_bytes", "coded_qr_encode", "coded_qr_factor", "coded_qr_ws_info",
     "coded_qr_erase", "coded_qr_recover", "coded_qr_postorth", "coded_qr_status_string",
     "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name", "coded_qr_solve",
-    "coded_qr_solve_workspace_bytes",
+    "coded_qr_solve_workspace_bytes", "coded_qr_backward", "coded_qr_backward_workspace_bytes",
+    "coded_qr_solve_backward", "coded_qr_solve_backward_workspace_bytes",
 ]
 
 PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram", "panel_chol", "panel_transform",
           "inpanel_projection", "trailing_product", "trailing_update", "split_reduce", "recover", "postorth",
-          "erase", "other", "panel_reencode", "solve"]
+          "erase", "other", "panel_reencode", "solve", "adjoint"]
 
 
 class CqrError(RuntimeError):
@@ -73,6 +74,11 @@ def _load() -> ctypes.CDLL:
         "coded_qr_postorth": (I32, [P, D, I64, D, I64, D, I64, D, I64, I32, V]),
         "coded_qr_solve": (I32, [P, D, I64, D, I64, D, I64, I32, D, I64, V, ctypes.c_size_t, V]),
         "coded_qr_solve_workspace_bytes": (ctypes.c_size_t, [P, I32]),
+        "coded_qr_backward_workspace_bytes": (ctypes.c_size_t, [P]),
+        "coded_qr_backward": (I32, [P, D, I64, D, I64, D, I64, D, I64, D, I64, V, ctypes.c_size_t, V]),
+        "coded_qr_solve_backward_workspace_bytes": (ctypes.c_size_t, [P, I32]),
+        "coded_qr_solve_backward": (I32, [P, D, I64, D, I64, D, I64, D, I64, D, I64, I32, D, I64, D, I64, D, I64,
+                                          V, ctypes.c_size_t, V]),
         "coded_qr_status_string": (ctypes.c_char_p, [I32]),
         "coded_qr_hip_error_name": (ctypes.c_char_p, []),
         "coded_qr_profile_enable": (I32, [P, I32]),
@@ -265,6 +271,27 @@ def coded_qr_solve(plan: int, Qpost, R, Bpost, X, ws, stream=None) -> int:
                               ws.numel() * ws.element_size(), ctypes.c_void_p(_stream(stream)))
 
 
+def coded_qr_backward_workspace_bytes(plan: int) -> int:
+    return LIB.coded_qr_backward_workspace_bytes(ctypes.c_void_p(plan))
+
+
+def coded_qr_backward(plan: int, Q, R, dQ, dR, dA, ws, stream=None) -> int:
+    return LIB.coded_qr_backward(ctypes.c_void_p(plan), _ptr(Q), _ld(Q), _ptr(R), _ld(R), _ptr(dQ), _ld(dQ),
+                                 _ptr(dR), _ld(dR), _ptr(dA), _ld(dA), _ptr(ws), ws.numel() * ws.element_size(),
+                                 ctypes.c_void_p(_stream(stream)))
+
+
+def coded_qr_solve_backward_workspace_bytes(plan: int, nrhs: int) -> int:
+    return LIB.coded_qr_solve_backward_workspace_bytes(ctypes.c_void_p(plan), nrhs)
+
+
+def coded_qr_solve_backward(plan: int, Qpost, R, Bpost, X, dX, dQ, dR, dB, ws, stream=None) -> int:
+    return LIB.coded_qr_solve_backward(ctypes.c_void_p(plan), _ptr(Qpost), _ld(Qpost), _ptr(R), _ld(R),
+                                       _ptr(Bpost), _ld(Bpost), _ptr(X), _ld(X), _ptr(dX), _ld(dX), X.shape[1],
+                                       _ptr(dQ), _ld(dQ), _ptr(dR), _ld(dR), _ptr(dB), _ld(dB), _ptr(ws),
+                                       ws.numel() * ws.element_size(), ctypes.c_void_p(_stream(stream)))
+
+
 def coded_qr_profile_enable(plan: int, enable: bool) -> int:
     return LIB.coded_qr_profile_enable(ctypes.c_void_p(plan), int(bool(enable)))
 
@@ -352,6 +379,28 @@ class CodedQR:
         ws = self.solve_workspace(nrhs) if ws is None else ws
         _check(coded_qr_solve(self.plan, Qpost, R, Bpost, X, ws), "coded_qr_solve")
         return X
+
+    def _bytes_buffer(self, nbytes: int):
+        import torch
+        return torch.empty(((nbytes + 7) // 8,), dtype=torch.float64, device=self.device)
+
+    def backward(self, Q, R, dQ, dR, dA=None):
+        """dA (m x n) from the cotangents of Q~[:, :n] and R_1 (coded_qr_backward)."""
+        dA = col_major(self.cfg.m, self.cfg.n, self.device) if dA is None else dA
+        ws = self._bytes_buffer(coded_qr_backward_workspace_bytes(self.plan))
+        _check(coded_qr_backward(self.plan, Q, R, dQ, dR, dA, ws), "coded_qr_backward")
+        return dA
+
+    def solve_backward(self, Qpost, R, Bpost, X, dX):
+        """(dQ~ (m' x n), dR_1 (n x n), dB (m x nrhs)) from dX (coded_qr_solve_backward)."""
+        c = self.cfg
+        dQ = col_major(c.mp, c.n, self.device)
+        dR = col_major(c.n, c.n, self.device)
+        dB = col_major(c.m, X.shape[1], self.device)
+        ws = self._bytes_buffer(coded_qr_solve_backward_workspace_bytes(self.plan, X.shape[1]))
+        _check(coded_qr_solve_backward(self.plan, Qpost, R, Bpost, X, dX, dQ, dR, dB, ws),
+               "coded_qr_solve_backward")
+        return dQ, dR, dB
 
     def run(self, A_dev, schedule=(), B=None):
         """encode -> factor with scheduled erasures/recoveries -> post-orth.

@@ -43,8 +43,9 @@ struct cqr_plan_s {
 };
 
 enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_CHOL, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
-             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_REENCODE, PH_SOLVE };
-static_assert(PH_SOLVE + 1 == CQR_NPHASES, "phase list and header disagree");
+             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_REENCODE, PH_SOLVE,
+             PH_ADJOINT };
+static_assert(PH_ADJOINT + 1 == CQR_NPHASES, "phase list and header disagree");
 
 namespace {
 
@@ -851,5 +852,133 @@ cqr_status coded_qr_solve(cqr_plan p, const double* Qpost, int64_t ldqp, const d
   }
   return hip_status();
 }
+
+}  // extern "C"
+
+namespace {
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Rinv = R_1^{-1} (n x n, ld n): diagonal blocks inverted at once, then the
+// block back substitution with the identity as right-hand side (Ytmp, n x n).
+void upper_inverse(cqr_plan_s& p, const double* R, int64_t ldr, double* Rinv, double* Ytmp, double* T,
+                   hipStream_t st) {
+  const int64_t n = p.cfg.n, nb = (n + 63) / 64;
+  prof(p, PH_ADJOINT, 0.0, 8.0 * n * n, st, [&] { cqr::launch_eye(Ytmp, n, n, st); });
+  prof(p, PH_ADJOINT, nb * 64.0 * 64 * 64 / 3, 8.0 * (n * 64.0 + nb * 64.0 * 64), st,
+       [&] { cqr::launch_trinv(R, ldr, n, T, st); });
+  for (int64_t k0 = (nb - 1) * 64; k0 >= 0; k0 -= 64) {
+    const int w = (int)std::min<int64_t>(64, n - k0);
+    prof(p, PH_ADJOINT, 2.0 * (64.0 * w + k0 * w) * n, 8.0 * (k0 * w + 2.0 * (k0 + w) * n), st,
+         [&] { cqr::launch_trsv_step(R, ldr, T, Ytmp, n, Rinv, n, (int)n, k0, w, st); });
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t coded_qr_backward_workspace_bytes(cqr_plan p) {
+  if (!p) return 0;
+  const size_t n = (size_t)p->cfg.n, mp = (size_t)p->mp, nb = (n + 63) / 64;
+  return up256(p->ws_bytes) + 3 * up256(8 * n * n) + up256(8 * nb * 64 * 64) + 2 * up256(8 * mp * n);
+}
+
+cqr_status coded_qr_backward(cqr_plan p, const double* Q, int64_t ldq, const double* R, int64_t ldr,
+                             const double* dQ, int64_t lddq, const double* dR, int64_t lddr, double* dA,
+                             int64_t ldda, void* ws, size_t ws_bytes, hipStream_t st) {
+  drop_pending_error();
+  if (!p || !Q || !R || !dQ || !dR || !dA || !ws) return CQR_EINVAL;
+  const int64_t m = p->cfg.m, n = p->cfg.n, mp = p->mp, nb = (n + 63) / 64;
+  if (ldq < mp || ldr < n || lddq < mp || lddr < n || ldda < m) return CQR_EINVAL;
+  if (ws_bytes < coded_qr_backward_workspace_bytes(p) || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return CQR_ENOMEM;
+  const cqr::Scratch s = scratch_of(*p, ws);
+  char* w = static_cast<char*>(ws) + up256(p->ws_bytes);
+  auto take = [&](size_t bytes) { double* q = reinterpret_cast<double*>(w); w += up256(bytes); return q; };
+  double* Rinv = take(8 * (size_t)n * n);
+  double* W1 = take(8 * (size_t)n * n);
+  double* W2 = take(8 * (size_t)n * n);
+  double* T = take(8 * (size_t)nb * 64 * 64);
+  double* D = take(8 * (size_t)mp * n);
+  double* X = take(8 * (size_t)mp * n);
+  const double nn2 = 8.0 * n * n;
+  upper_inverse(*p, R, ldr, Rinv, W1, T, st);
+  // W2 = M1 = Q~^T dQ~
+  tn(*p, PH_ADJOINT, Q, ldq, dQ, lddq, (int)n, (int)n, mp, W2, n, nullptr, 0, s, st);
+  // W1 = M1^T;  W2 = triu(dR)^T;  W1 -= R W2, so W1 = dQ~^T Q~ - R dR^T = -M
+  prof(*p, PH_ADJOINT, 0.0, 2 * nn2, st, [&] { cqr::launch_transpose(W2, n, W1, n, n, n, 1.0, false, st); });
+  prof(*p, PH_ADJOINT, 0.0, 2 * nn2, st, [&] { cqr::launch_transpose(dR, lddr, W2, n, n, n, 1.0, true, st); });
+  nn(*p, PH_ADJOINT, W1, n, R, ldr, W2, n, n, (int)n, (int)n, s, st);
+  // W1 <- copyltu(W1) = -copyltu(M)
+  prof(*p, PH_ADJOINT, 0.0, nn2, st, [&] { cqr::launch_copyltu(W1, n, n, st); });
+  // D = dQ~ - Q~ W1 = dQ~ + Q~ copyltu(M)
+  {
+    hipError_t e = hipMemcpy2DAsync(D, 8 * mp, dQ, 8 * lddq, 8 * mp, n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  nn(*p, PH_ADJOINT, D, mp, Q, ldq, W1, n, mp, (int)n, (int)n, s, st);
+  // W2 = -R^{-T};  X = 0;  X -= D W2, so X = D R^{-T} = dA~
+  prof(*p, PH_ADJOINT, 0.0, 2 * nn2, st, [&] { cqr::launch_transpose(Rinv, n, W2, n, n, n, -1.0, false, st); });
+  prof(*p, PH_ADJOINT, 0.0, 8.0 * mp * n, st, [&] { cqr::launch_fill_zero(X, mp, mp, n, st); });
+  nn(*p, PH_ADJOINT, X, mp, D, mp, W2, n, mp, (int)n, (int)n, s, st);
+  // dA = dA~_top + G_v^T dA~_bottom
+  cqr::FoldArgs f{};
+  f.X = X; f.ldx = mp; f.dA = dA; f.ldd = ldda;
+  f.m = m; f.bs = p->bs; f.cols = n; f.pr = p->cfg.pr; f.kv = p->cfg.kv;
+  for (size_t e = 0; e < p->gv.size(); ++e) f.gv[e] = p->gv[e];
+  prof(*p, PH_ADJOINT, 2.0 * f.kv * m * n, 8.0 * (mp + m) * n, st, [&] { cqr::launch_fold(f, st); });
+  return hip_status();
+}
+
+size_t coded_qr_solve_backward_workspace_bytes(cqr_plan p, int32_t nrhs) {
+  if (!p || nrhs < 1) return 0;
+  const size_t n = (size_t)p->cfg.n, nb = (n + 63) / 64;
+  return 2 * up256(8 * n * n) + up256(8 * nb * 64 * 64) + up256(8 * n * (size_t)nrhs);
+}
+
+cqr_status coded_qr_solve_backward(cqr_plan p, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
+                                   const double* Bpost, int64_t ldbp, const double* X, int64_t ldx,
+                                   const double* dX, int64_t lddx, int32_t nrhs, double* dQ, int64_t lddq,
+                                   double* dR, int64_t lddr, double* dB, int64_t lddb, void* ws, size_t ws_bytes,
+                                   hipStream_t st) {
+  drop_pending_error();
+  if (!p || !Qpost || !R || !Bpost || !X || !dX || !dQ || !dR || !dB || !ws || nrhs < 1 || p->cfg.kv == 0)
+    return CQR_EINVAL;
+  const int64_t m = p->cfg.m, n = p->cfg.n, mp = p->mp, nb = (n + 63) / 64;
+  if (ldqp < m || ldr < n || ldbp < m || ldx < n || lddx < n || lddq < mp || lddr < n || lddb < m)
+    return CQR_EINVAL;
+  if (ws_bytes < coded_qr_solve_backward_workspace_bytes(p, nrhs) || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return CQR_ENOMEM;
+  char* w = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) { double* q = reinterpret_cast<double*>(w); w += up256(bytes); return q; };
+  double* Rinv = take(8 * (size_t)n * n);
+  double* Ytmp = take(8 * (size_t)n * n);
+  double* T = take(8 * (size_t)nb * 64 * 64);
+  double* DY = take(8 * (size_t)n * nrhs);
+  upper_inverse(*p, R, ldr, Rinv, Ytmp, T, st);
+  // dy = R_1^{-T} dX = Rinv^T dX
+  prof(*p, PH_ADJOINT, 2.0 * n * n * nrhs, 8.0 * (n * n + 2.0 * n * nrhs), st,
+       [&] { cqr::launch_gemv_t(Rinv, n, n, (int)n, dX, lddx, nrhs, DY, n, st); });
+  // dR_1 = -triu(dy x^T)
+  prof(*p, PH_ADJOINT, 2.0 * n * n * nrhs, 8.0 * n * n, st,
+       [&] { cqr::launch_outer(DY, n, X, ldx, n, n, nrhs, -1.0, true, dR, lddr, st); });
+  // dQ~[:m] = G_0 (Bpost dy^T), dQ~[m:] = 0
+  prof(*p, PH_ADJOINT, 2.0 * m * n * nrhs, 8.0 * m * n, st,
+       [&] { cqr::launch_outer(Bpost, ldbp, DY, n, m, n, nrhs, 1.0, false, dQ, lddq, st); });
+  cqr::PostArgs a{};
+  a.pr = p->cfg.pr; a.kv = p->cfg.kv; a.bs = p->bs;
+  for (size_t e = 0; e < p->gv.size(); ++e) a.gv[e] = p->gv[e];
+  a.src = dQ; a.lds = lddq; a.dst = dQ; a.ldd = lddq; a.cols = n;
+  prof(*p, PH_ADJOINT, 0.0, 16.0 * m * n, st, [&] { cqr::launch_postorth(a, st); });
+  prof(*p, PH_ADJOINT, 0.0, 8.0 * (mp - m) * n, st, [&] { cqr::launch_fill_zero(dQ + m, lddq, mp - m, n, st); });
+  // dB = G_0 (Qpost dy)
+  prof(*p, PH_ADJOINT, 2.0 * m * n * nrhs, 8.0 * (m * n + m * nrhs), st,
+       [&] { cqr::launch_gemv_n(Qpost, ldqp, m, (int)n, DY, n, nrhs, dB, lddb, st); });
+  a.src = dB; a.lds = lddb; a.dst = dB; a.ldd = lddb; a.cols = nrhs;
+  prof(*p, PH_ADJOINT, 0.0, 16.0 * m * nrhs, st, [&] { cqr::launch_postorth(a, st); });
+  return hip_status();
+}
+
 
 }  // extern "C"

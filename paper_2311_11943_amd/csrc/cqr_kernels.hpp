@@ -50,6 +50,17 @@ struct PostArgs {
   double gv[kMaxGen * kMaxGrid];   // G~_v = [G~_1  V~], K_v x p_r row-major
 };
 
+// dA = X_top + G_v^T X_bottom (encoding adjoint), X with m + K_v bs rows.
+struct FoldArgs {
+  const double* X;
+  int64_t ldx;
+  double* dA;
+  int64_t ldd;
+  int64_t m, bs, cols;
+  int pr, kv;
+  double gv[kMaxGen * kMaxGrid];   // G~_v, K_v x p_r row-major
+};
+
 // Scratch regions inside the caller's workspace (all device pointers).
 struct Scratch {
   int* info;          // [0]: breakdown flag (0 or 1 + panel)
@@ -128,6 +139,16 @@ void launch_postorth(const PostArgs& a, hipStream_t st);
 void launch_gemv_t(const double* Q, int64_t ldq, int64_t m, int n, const double* B, int64_t ldb, int nrhs,
                    double* Y, int64_t ldy, hipStream_t st);
 void launch_trinv(const double* R, int64_t ldr, int64_t n, double* T, hipStream_t st);
+// adjoint helpers
+void launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
+                      double scale, bool upper, hipStream_t st);
+void launch_copyltu(double* C, int64_t ldc, int64_t n, hipStream_t st);
+void launch_outer(const double* U, int64_t ldu, const double* V, int64_t ldv, int64_t rows, int64_t cols, int k,
+                  double scale, bool upper, double* C, int64_t ldc, hipStream_t st);
+void launch_gemv_n(const double* A, int64_t lda, int64_t m, int n, const double* x, int64_t ldx, int nrhs,
+                   double* y, int64_t ldy, hipStream_t st);
+void launch_fold(const FoldArgs& a, hipStream_t st);
+void launch_eye(double* Y, int64_t ldy, int64_t n, hipStream_t st);
 void launch_trsv_step(const double* R, int64_t ldr, const double* T, double* Y, int64_t ldy, double* X,
                       int64_t ldx, int nrhs, int64_t k0, int w, hipStream_t st);
 

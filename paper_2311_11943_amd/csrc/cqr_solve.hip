@@ -4,10 +4,12 @@
 //      (one workgroup per block, column-oriented substitution in LDS).
 //   2. gemv_t_kernel: Y = Qpost^T Bpost, one wave per column of Qpost (its m
 //      entries are contiguous), partial sums reduced across the wave.
-//   3. Block back substitution, bottom-up, one launch per 64-row block k:
-//      every workgroup forms x_k = T_kk y_k (T_kk = R_kk^{-1}) in LDS, the
-//      first one stores it, and each thread subtracts R_1[i, block k] x_k from
-//      its row i < k0 of Y (loads of a column of R coalesced across the wave).
+//   3. Block back substitution, bottom-up, one launch per 64-row block k
+//      (right-hand sides in groups of 4 along the grid's y dimension): every
+//      workgroup forms x_k = T_kk y_k (T_kk = R_kk^{-1}) in LDS, the first
+//      column of workgroups stores it, and each thread subtracts
+//      R_1[i, block k] x_k from its row i < k0 of Y (loads of a column of R
+//      coalesced across the wave).
 #include "cqr_kernels.hpp"
 
 namespace cqr {
@@ -95,8 +97,9 @@ __global__ __launch_bounds__(kSolveThreads) void trinv_kernel(const double* R, i
     out[e] = Tl[e % kSolveBlock][e / kSolveBlock];
 }
 
-// Block k0 of the back substitution: x = T_kk Y[k0:k0+w] -> X[k0:k0+w] (first
-// workgroup), Y[0:k0] -= R_1[0:k0, k0:k0+w] x (one thread per row).
+// Block k0 of the back substitution for right-hand sides r0 .. r0+3
+// (r0 = 4 blockIdx.y): x = T_kk Y[k0:k0+w] -> X[k0:k0+w] (workgroups with
+// blockIdx.x == 0), Y[0:k0] -= R_1[0:k0, k0:k0+w] x (one thread per row).
 __global__ __launch_bounds__(kSolveThreads) void trsv_step_kernel(const double* R, int64_t ldr, const double* T,
                                                                   double* Y, int64_t ldy, double* X, int64_t ldx,
                                                                   int nrhs, int64_t k0, int w) {
@@ -108,43 +111,40 @@ __global__ __launch_bounds__(kSolveThreads) void trsv_step_kernel(const double* 
   for (int e = tid; e < kSolveBlock * kSolveBlock; e += kSolveThreads)
     Tl[e % kSolveBlock][e / kSolveBlock] = Tk[e];
   const int row = tid & 63, u = tid >> 6;
-  const int64_t i = (int64_t)blockIdx.x * kSolveThreads + tid;
-  const double* ri = R + i + k0 * ldr;
-  for (int r0 = 0; r0 < nrhs; r0 += kRhsChunk) {
-    const bool mine = row < w && r0 + u < nrhs;
-    yk[row][u] = mine ? Y[k0 + row + (int64_t)(r0 + u) * ldy] : 0.0;
-    __syncthreads();
-    double x = 0.0;
+  const int r0 = blockIdx.y * kRhsChunk;
+  const bool mine = row < w && r0 + u < nrhs;
+  yk[row][u] = mine ? Y[k0 + row + (int64_t)(r0 + u) * ldy] : 0.0;
+  __syncthreads();
+  double x = 0.0;
 #pragma unroll 16
-    for (int t = 0; t < kSolveBlock; ++t) x += Tl[row][t] * yk[t][u];
-    xk[row][u] = x;
-    if (blockIdx.x == 0 && mine) X[k0 + row + (int64_t)(r0 + u) * ldx] = x;
-    __syncthreads();
-    if (i < k0) {
-      double acc[kRhsChunk] = {0.0, 0.0, 0.0, 0.0};
-      if (w == kSolveBlock) {
-        // every load of the row's 64 coefficients in flight before the sums
-        double v[kSolveBlock];
+  for (int t = 0; t < kSolveBlock; ++t) x += Tl[row][t] * yk[t][u];
+  xk[row][u] = x;
+  if (blockIdx.x == 0 && mine) X[k0 + row + (int64_t)(r0 + u) * ldx] = x;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kSolveThreads + tid;
+  if (i >= k0) return;
+  const double* ri = R + i + k0 * ldr;
+  double acc[kRhsChunk] = {0.0, 0.0, 0.0, 0.0};
+  if (w == kSolveBlock) {
+    // every load of the row's 64 coefficients in flight before the sums
+    double v[kSolveBlock];
 #pragma unroll
-        for (int t = 0; t < kSolveBlock; ++t) v[t] = ri[t * ldr];
-        __builtin_amdgcn_sched_barrier(0);
+    for (int t = 0; t < kSolveBlock; ++t) v[t] = ri[t * ldr];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int t = 0; t < kSolveBlock; ++t)
+    for (int t = 0; t < kSolveBlock; ++t)
 #pragma unroll
-          for (int q = 0; q < kRhsChunk; ++q) acc[q] += v[t] * xk[t][q];
-      } else {
-        for (int t = 0; t < w; ++t) {
-          const double v = ri[t * ldr];
+      for (int q = 0; q < kRhsChunk; ++q) acc[q] += v[t] * xk[t][q];
+  } else {
+    for (int t = 0; t < w; ++t) {
+      const double v = ri[t * ldr];
 #pragma unroll
-          for (int q = 0; q < kRhsChunk; ++q) acc[q] += v * xk[t][q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kRhsChunk; ++q)
-        if (r0 + q < nrhs) Y[i + (int64_t)(r0 + q) * ldy] -= acc[q];
+      for (int q = 0; q < kRhsChunk; ++q) acc[q] += v * xk[t][q];
     }
-    __syncthreads();
   }
+#pragma unroll
+  for (int q = 0; q < kRhsChunk; ++q)
+    if (r0 + q < nrhs) Y[i + (int64_t)(r0 + q) * ldy] -= acc[q];
 }
 
 void launch_gemv_t(const double* Q, int64_t ldq, int64_t m, int n, const double* B, int64_t ldb, int nrhs,
@@ -162,8 +162,9 @@ void launch_trinv(const double* R, int64_t ldr, int64_t n, double* T, hipStream_
 void launch_trsv_step(const double* R, int64_t ldr, const double* T, double* Y, int64_t ldy, double* X,
                       int64_t ldx, int nrhs, int64_t k0, int w, hipStream_t st) {
   const unsigned grid = k0 > 0 ? (unsigned)((k0 + kSolveThreads - 1) / kSolveThreads) : 1u;
-  hipLaunchKernelGGL(trsv_step_kernel, dim3(grid), dim3(kSolveThreads), 0, st, R, ldr, T, Y, ldy, X, ldx, nrhs,
-                     k0, w);
+  const unsigned chunks = (unsigned)((nrhs + kRhsChunk - 1) / kRhsChunk);
+  hipLaunchKernelGGL(trsv_step_kernel, dim3(grid, chunks), dim3(kSolveThreads), 0, st, R, ldr, T, Y, ldy, X, ldx,
+                     nrhs, k0, w);
 }
 
 }  // namespace cqr
