@@ -222,6 +222,87 @@ def run_sweep(args):
             torch.cuda.empty_cache()
 
 
+def run_adjoint(args):
+    """Tall-skinny least squares through the coded QR and its adjoint:
+    m = 65536, n = 512 Gaussian A and b, 16 x 1 grid (4096-row blocks), b = 64,
+    K_v = 2 out-of-node checksum block rows, no horizontal code (p_c = 1).
+    loss = ||x - x_t||^2 with x = R_1^{-1} (G_0 Q_1)^T (G_0 b); the forward
+    (encode, factor, post-orthogonalization, solve) and the backward
+    (coded_qr_solve_backward, coded_qr_backward) are timed separately, and the
+    gradient is checked against the closed form of the W-weighted least squares
+    (W = I + G_v^T G_v).  One JSON line."""
+    import torch
+    from paper_2311_11943_amd import autograd as ag
+    from paper_2311_11943_amd import cqr
+    dev = torch.device("cuda:0")
+    m, n, pr, K, b = 65536, 512, 16, 2, 64
+    cfg = cqr.Config(m, n, pr, 1, K, 0, b, cqr.CQR_OUT_OF_NODE)
+    v = synth.q_generator_draws(K, pr, args.seed)
+    engine = cqr.CodedQR(cfg, v, None, dev)
+    A = torch.tensor(synth.gaussian(m, n, args.seed), device=dev, requires_grad=True)
+    B = torch.tensor(synth.gaussian(m, 1, args.seed + 1), device=dev, requires_grad=True)
+    xt = torch.tensor(synth.gaussian(n, 1, args.seed + 2), device=dev)
+
+    def fwd():
+        Q, R1 = ag.coded_qr(A, engine)
+        return ag.coded_solve(Q, R1, B, engine)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    f_ms, b_ms = [], []
+    for it in range(args.warmup + args.steps):
+        A.grad = None
+        B.grad = None
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        x = fwd()
+        loss = ((x - xt) ** 2).sum()
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            f_ms.append(e0.elapsed_time(e1))
+            b_ms.append(e1.elapsed_time(e2))
+    fm, bm = sum(f_ms) / len(f_ms), sum(b_ms) / len(b_ms)
+    # closed form: W v = v + G_v^T (G_v v), with G_v = G~_v (x) I_bs
+    gv = torch.tensor(engine.generators()[0], device=dev)
+    bs = m // pr
+
+    def W(vm):
+        vm = vm.detach()
+        blocks = vm.reshape(pr, -1)                  # block t of rows in row t
+        chk = gv @ blocks                            # G_v v, one row per checksum block
+        return vm + (gv.T @ chk).reshape(m, -1)
+
+    Ad, Bd = A.detach(), B.detach()
+    WA = W(Ad)
+    H = Ad.T @ WA
+    xw = torch.linalg.solve(H, WA.T @ Bd)
+    z = torch.linalg.solve(H, 2 * (xw - xt))
+    cA = W(Bd - Ad @ xw) @ z.T - WA @ z @ xw.T
+    cB = WA @ z
+    relA = ((A.grad - cA).abs().max() / cA.abs().max()).item()
+    relB = ((B.grad - cB).abs().max() / cB.abs().max()).item()
+    relx = ((x.detach() - xw).abs().max() / xw.abs().max()).item()
+    mp = cfg.mp
+    f_fl = model_flops(mp, n, 0, b) + 2.0 * m * n + n * n
+    b_fl = 6.0 * mp * n * n + 2.0 * n ** 3
+    print(json.dumps({
+        "metric": "coded-QR least-squares forward + adjoint time", "value": round(fm + bm, 4), "unit": "ms",
+        "higher_is_better": False, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c4: m=65536, n=512 Gaussian A and b, 16x1 grid (4096-row blocks), b=64, "
+                               "K_v=2 out-of-node, no horizontal code, failure free",
+                   "m": m, "n": n, "grid": "16x1", "b": b, "K_v": K},
+        "forward_ms": round(fm, 4), "backward_ms": round(bm, 4),
+        "forward_tflops": round(f_fl / (fm * 1e-3) / 1e12, 3), "backward_tflops": round(b_fl / (bm * 1e-3) / 1e12, 3),
+        "errors": {"x_vs_weighted_ls": relx, "dA_vs_closed_form": relA, "db_vs_closed_form": relB},
+    }), flush=True)
+    engine.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +326,9 @@ def main():
                     help="instead of the benchmark line: the paper's coding-overhead grid (n = 24000, "
                          "p in {6, 8, 10, 12}, f in {0..3}), one JSON line per point")
     ap.add_argument("--sweep-n", type=int, default=24000)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the benchmark line: forward + adjoint of the tall-skinny least-squares "
+                         "workload (m = 65536, n = 512), one JSON line")
     ap.add_argument("--reps", type=int, default=5, help="repetitions of each timed extra (overhead legs)")
     args = ap.parse_args()
 
@@ -255,6 +339,9 @@ def main():
 
     if args.sweep:
         run_sweep(args)
+        return
+    if args.adjoint:
+        run_adjoint(args)
         return
 
     import torch
