@@ -296,6 +296,11 @@ int tag_of(int phase) {
   return cqr::TAG_PANEL;
 }
 
+// Products of the panel chain (everything but the bulk trailing update) run
+// their waves at raised issue priority: while they share compute units with
+// the update stream's kernels, the chain sets the pace of the factorization.
+int chain_phase(int phase) { return phase != PH_TRAIL_TN && phase != PH_TRAIL_NN; }
+
 double partial_bytes(int nsplit, int ntiles) { return 8.0 * nsplit * ntiles * cqr::kTile * cqr::kTile; }
 
 void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N,
@@ -304,6 +309,7 @@ void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B,
   if (M <= 0 || N <= 0) return;
   cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s, 0, f32);
   if (M2 >= 0) a.M2 = M2;
+  a.prio = chain_phase(phase);
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N);
   const double out = 8.0 * (double)M * N * (C2 ? 3.0 : 1.0);
   const int tag = tag_of(phase);
@@ -319,7 +325,8 @@ void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B,
 void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64_t lda, const double* B,
         int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st, bool f32 = false) {
   if (M <= 0 || N <= 0 || K <= 0) return;
-  const cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, f32);
+  cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, f32);
+  a.prio = chain_phase(phase);
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)M * K + (double)K * N);
   const double upd = 16.0 * (double)M * N;
   const int tag = tag_of(phase);

@@ -138,6 +138,7 @@ __device__ __forceinline__ void tn_store(const TnArgs& a, const Acc (&acc)[2][2]
 
 template <int TAG, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void tn_lds_kernel(TnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
   typedef typename AccT<F32>::type Acc;
   __shared__ double sA[2][64 * LDP];
   __shared__ double sB[2][64 * LDP];
@@ -264,6 +265,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // Fallback for operands that are not 16-byte aligned or have odd leading
 // dimensions: direct scalar loads, same tiling and output contract.
 __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
   const int tile = blockIdx.x, split = blockIdx.y;
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
@@ -311,6 +313,7 @@ __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
 // Sum the split partials in split order; write C (and C2 +=).  One block per
 // wave quadrant of a tile, thread (qg, lane) owns 4 of the lane's 16 values.
 __global__ __launch_bounds__(256) void tn_reduce_kernel(TnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
   const int tile = blockIdx.x >> 2, wave = blockIdx.x & 3;
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
   const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
@@ -558,6 +561,7 @@ __device__ __forceinline__ void tmul_global_store(int tid, const double (*Tl)[kL
 }
 
 __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
+  __builtin_amdgcn_s_setprio(2);   // the panel chain sets the pace of the factorization
   __shared__ double Rl[kLeaf][kLeaf + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
   __shared__ double rowW[2][kLeaf];
@@ -649,6 +653,7 @@ void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, in
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void apply_kernel(double* P, int64_t ldp, int64_t mrows, int w,
                                                     const double* T) {
+  __builtin_amdgcn_s_setprio(2);   // panel chain
   __shared__ double tileP[kLeaf][64 + 1];   // [col][row]
   __shared__ double tileT[kLeaf][kLeaf + 1];   // [k][j]
   const int64_t r0 = (int64_t)blockIdx.x * 64;
@@ -730,10 +735,10 @@ struct NnTile {
   const double* bp;   // B[16(t & 3)][jb + (t >> 2)]
 };
 
-__device__ __forceinline__ NnTile nn_tile(const NnArgs& a, int tile) {
+__device__ __forceinline__ NnTile nn_tile_at(const NnArgs& a, int tm, int tn) {
   NnTile t;
-  t.tm = tile / a.tilesN;
-  t.tn = tile % a.tilesN;
+  t.tm = tm;
+  t.tn = tn;
   t.tid = threadIdx.x;
   t.wave = t.tid >> 6;
   t.lane = t.tid & 63;
@@ -747,6 +752,29 @@ __device__ __forceinline__ NnTile nn_tile(const NnArgs& a, int tile) {
   const int jc = t.jb + (t.tid >> 2);
   t.bp = a.B + 16 * (t.tid & 3) + (int64_t)(jc < a.N ? jc : 0) * a.ldb;
   return t;
+}
+
+__device__ __forceinline__ NnTile nn_tile(const NnArgs& a, int tile) {
+  return nn_tile_at(a, tile / a.tilesN, tile % a.tilesN);
+}
+
+// XCD-aware tile order for one-pass updates.  Workgroups are dealt to the
+// eight XCDs round-robin (block b runs on XCD b mod 8), and each XCD has its
+// own L2.  Block b takes position start(x) + b / 8 of an order in which the
+// tiles come in four bands of row tiles, each band walked column slab by
+// column slab; XCD x's positions form one contiguous range of that order,
+// i.e. about half of one band.  Each XCD thus reads a quarter of the A rows
+// and half of the B columns instead of all of both.
+__device__ __forceinline__ void xcd_tile(int b, int ntiles, int tilesM, int tilesN, int& tm, int& tn) {
+  const int x = b & 7, j = b >> 3;
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int pos = x * q + (x < r ? x : r) + j;
+  const int bm = (tilesM + 3) >> 2;                 // row tiles per band
+  const int band = pos / (bm * tilesN);
+  const int rows = min(bm, tilesM - band * bm);     // rows in this band (the last may be short)
+  const int in = pos - band * bm * tilesN;
+  tn = in / rows;
+  tm = band * bm + in % rows;
 }
 
 __device__ __forceinline__ void nn_load_a(const NnArgs& a, const NnTile& t, int k0, double (&xa)[16]) {
@@ -796,9 +824,12 @@ __device__ __forceinline__ void nn_mma(Acc (&acc)[4], const double (*sBb)[64 + 1
 // (C, A, the B slab) is issued before the first product.
 template <int TAG, bool F32>
 __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
   typedef typename AccT<F32>::type Acc;
   __shared__ double sB[NK][64 + 1];
-  const NnTile t = nn_tile(a, blockIdx.x);
+  int tm, tn;
+  xcd_tile(blockIdx.x, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
+  const NnTile t = nn_tile_at(a, tm, tn);
   double cval[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -836,6 +867,7 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
 // nn_reduce_kernel; otherwise C is read at the end and updated in place.
 template <bool SPLIT, int TAG, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
   typedef typename AccT<F32>::type Acc;
   __shared__ double sB[2][NK][64 + 1];
   const int split = blockIdx.y;
@@ -911,6 +943,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // C -= sum of the split partials (split order).  One block per wave of a
 // tile, thread (qg, lane) owns the lane's 4 values of column block qg.
 __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
   const int tile = blockIdx.x >> 2, wave = blockIdx.x & 3;
   const int tm = tile / a.tilesN, tn = tile % a.tilesN;
   const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;

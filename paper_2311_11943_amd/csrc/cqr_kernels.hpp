@@ -88,6 +88,7 @@ struct TnArgs {
   double* part;
   int vec;            // both operands 16-byte aligned with even leading dimensions
   int f32;            // FP32 products (operands rounded), FP32 accumulation
+  int prio;           // raise the waves' issue priority (panel-chain products)
 };
 
 // Choose the split of C = A^T B (stored to C; rows below M2 -- all rows
@@ -112,6 +113,7 @@ struct NnArgs {
   int vec;            // B 16-byte aligned with even ldb (vector B loads)
   int f32;            // FP32 products (operands rounded), FP32 accumulation
   double* part;
+  int prio;           // raise the waves' issue priority (panel-chain products)
 };
 NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                 int N, int K, const Scratch& s, bool f32 = false);
