@@ -345,8 +345,10 @@ static bool aligned16(const void* p, int64_t ld) {
 }
 
 static int pick_split(int tiles, int64_t K, int64_t cap) {
-  // ~512 blocks (two per CU); each split keeps at least 256 rows (8 slabs)
-  int want = std::max(1, (512 + tiles - 1) / std::max(1, tiles));
+  // at most 512 blocks (two resident per CU, so one wave of blocks: a few
+  // blocks over that run as a second wave and cost ~16% at 79 tiles); each
+  // split keeps at least 256 rows (8 slabs)
+  int want = std::max(1, 512 / std::max(1, tiles));
   int64_t maxs = std::max<int64_t>(1, K / 256);
   int ns = (int)std::min<int64_t>(want, maxs);
   while (ns > 1 && (int64_t)ns * tiles > cap) --ns;
@@ -977,11 +979,11 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
   a.ntiles = (int)((M + 63) / 64) * a.tilesN;
   a.part = s.part;
   a.vec = aligned16(B, ldb);
-  // few tiles and a long reduction: split K so ~512 blocks (two per CU) run,
-  // each over at least 2 slabs
+  // few tiles and a long reduction: split K so at most 512 blocks (two per
+  // CU, one wave of blocks) run, each over at least 2 slabs
   int ns = 1;
   if (K > NK && a.ntiles < 512 && K >= 4 * NK) {
-    ns = (int)std::min<int64_t>((512 + a.ntiles - 1) / a.ntiles, K / (2 * NK));
+    ns = (int)std::min<int64_t>(std::max(1, 512 / a.ntiles), K / (2 * NK));
     while (ns > 1 && (int64_t)ns * a.ntiles > s.npart) --ns;
   }
   int kchunk = (K + ns - 1) / ns;
