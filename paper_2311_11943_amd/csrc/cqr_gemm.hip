@@ -400,7 +400,7 @@ void launch_tn_reduce(const TnArgs& a, hipStream_t st) {
 // --------------------------------------------------------------------------
 // Upper Cholesky factor of a panel leaf's Gram matrix W (w <= kLeaf), its
 // inverse, and on the second pass R2 R1 and the lookahead coefficients T^T X.
-// One block of four waves (see chol_aug for the elimination).  A
+// One block of four waves (see chol_blocked for the factorization).  A
 // non-positive pivot sets info[0] = 1 + panel (first occurrence kept) and the
 // factorization continues with pivot 1.
 // --------------------------------------------------------------------------
@@ -421,75 +421,130 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(y, r, y);
 }
 
-// Exact path.  Gauss elimination of the augmented matrix [W | I] with row j
-// scaled by 1/sqrt(pivot) when it becomes final: since W = R^T R, the same
-// row operations turn W into R and I into R^{-T}, so the Cholesky factor and
-// its inverse come out of one sweep of 64 steps.  Thread (tx, ty) holds
-// column tx of its rows of both halves in 16 register slots; the 64 steps
-// run as 16 groups of 4, pivot row 4G + t being slot 0 of threads ty = t,
-// and after each group the slots shift down by one (slot q then holds row
-// ty + 4(q + G)), so every register index is a compile-time constant.  The
-// current pivot row is published through LDS buffers alternating with the
-// step parity (one block barrier per step); each final row of R goes to Rl
-// and of R^{-T} (transposed, i.e. T = R^{-1}) to Tl.
-__device__ __forceinline__ void chol_aug(int tid, double (*rowW)[kLeaf], double (*rowZ)[kLeaf],
-                                         double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1], bool& bad) {
-  const int tx = tid & 63, ty = tid >> 6;
-  double c[16], d[16];
+// 16 x 16 block product on MFMA: acc += sum over k < 16 nk of A(i, k) B(k, j)
+// for the block's i, j < 16.  Lane (li, g) feeds A(li, k) and B(k, li) for
+// k = k0 + 4g + s, and holds C[li][4r + g] in acc[r] (the layout used
+// throughout this file).
+template <class FA, class FB>
+__device__ __forceinline__ void mma16(v4d& acc, int lane, int nk, FA A, FB B) {
+  const int li = lane & 15, g = lane >> 4;
+  for (int k0 = 0; k0 < 16 * nk; k0 += 16) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = ty + 4 * q;
-    c[q] = (i <= tx) ? Rl[i][tx] : Rl[tx][i];    // upper triangle of W, symmetrically
-    d[q] = (i == tx) ? 1.0 : 0.0;
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      acc = mfma(B(k, li), A(li, k), acc);
+    }
   }
-  if (ty == 0) {
-    rowW[0][tx] = c[0];
-    rowZ[0][tx] = d[0];
+}
+
+// One wave factors the 16 x 16 diagonal block at offset o of Rl (its upper
+// triangle, already updated, read symmetrically): Gauss elimination of the
+// augmented [D | I] with each final row scaled by 1/sqrt(pivot), so D = R^T R
+// gives R (into Rl's block, zero below the diagonal) and T = R^{-1} (into
+// Tl's block).  Lanes 0..15 hold column tx of D, lanes 16..31 column tx of
+// the identity half, 16 rows in registers.  Step j: the D lanes publish row j
+// (by symmetry also column j) through LDS, every lane reads the pivot and the
+// column-j factors, and subtracts.  Only the wave's own LDS traffic orders the
+// steps (in-order LDS within a wave), so there is no block barrier.
+__device__ __forceinline__ void chol_diag16(int lane, int o, double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1],
+                                            double* prow, bool& bad) {
+  const int tx = lane & 15;
+  const bool dl = lane < 16, zl = lane >= 16 && lane < 32;
+  double c[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    c[i] = dl ? ((i <= tx) ? Rl[o + i][o + tx] : Rl[o + tx][o + i]) : (zl && i == tx ? 1.0 : 0.0);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (dl) prow[tx] = c[j];
+    __builtin_amdgcn_wave_barrier();
+    double piv = prow[j];
+    double fac[16];
+#pragma unroll
+    for (int i = j + 1; i < 16; ++i) fac[i] = prow[i];
+    __builtin_amdgcn_wave_barrier();
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      bad = true;
+      piv = 1.0;
+    }
+    const double inv = rsqrt_nr(piv);
+    const double f = c[j] * inv * inv;
+#pragma unroll
+    for (int i = j + 1; i < 16; ++i) c[i] -= fac[i] * f;
+    if (dl) Rl[o + j][o + tx] = (tx >= j) ? c[j] * inv : 0.0;
+    if (zl) Tl[o + tx][o + j] = c[j] * inv;
   }
+}
+
+// Exact path: blocked right-looking Cholesky of the 64 x 64 W in Rl (16 x 16
+// blocks) and the inverse T = R^{-1} in Tl.  Block step b: wave 0 factors the
+// diagonal block (R_bb, T_bb); the row panel R_bc = T_bb^T W_bc (c > b) and
+// the trailing update W_cd -= R_bc^T R_bd (b < c <= d) run on MFMA, one
+// 16 x 16 block per wave.  Then T's off-diagonal blocks, one block column per
+// wave: T_ab = -T_aa sum_{c=a+1..b} R_ac T_cb for a = b-1 down to 0.  About a
+// dozen block barriers instead of one per pivot.
+__device__ __forceinline__ void chol_blocked(int tid, double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1],
+                                             double* prow, bool& bad) {
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
 #pragma unroll 1
-  for (int G = 0; G < 16; ++G) {
+  for (int b = 0; b < 4; ++b) {
+    const int o = 16 * b;
+    if (wave == 0) chol_diag16(lane, o, Rl, Tl, prow, bad);
+    __syncthreads();
+    // row panel R_bc = T_bb^T W_bc, in place
+    const int c = b + 1 + wave;
+    if (c < 4) {
+      v4d acc = v4d{0, 0, 0, 0};
+      mma16(acc, lane, 1, [&](int i, int k) { return Tl[o + k][o + i]; },
+            [&](int k, int j) { return Rl[o + k][16 * c + j]; });
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = 4 * G + t, par = t & 1;
-      __syncthreads();
-      double piv = rowW[par][j];
-      const double wx = rowW[par][tx], zx = rowZ[par][tx];
-      double wi[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) wi[q] = rowW[par][(ty + 4 * (q + G)) & 63];   // wrapped rows: unused slots
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        bad = true;
-        piv = 1.0;
-      }
-      const double inv = rsqrt_nr(piv);
-      const double inv2 = inv * inv;
-      const double fw = wx * inv2, fz = zx * inv2;
-      // the slot holding the next pivot row first, so its owner publishes early
-      const int sn = (t < 3) ? 0 : 1;
-      const bool below = (t < 3) ? (ty > t) : true;   // slot sn holds a row below j
-      c[sn] -= wi[sn] * (below ? fw : 0.0);
-      d[sn] -= wi[sn] * (below ? fz : 0.0);
-      if (ty == ((t + 1) & 3) && j + 1 < kLeaf) {
-        rowW[par ^ 1][tx] = c[sn];
-        rowZ[par ^ 1][tx] = d[sn];
-      }
-      if (ty == t) {
-        Rl[j][tx] = (tx > j) ? wx * inv : (tx == j ? piv * inv : 0.0);
-        Tl[tx][j] = zx * inv;
-      }
-#pragma unroll
-      for (int q = sn + 1; q < 16; ++q) {
-        c[q] -= wi[q] * fw;
-        d[q] -= wi[q] * fz;
-      }
+      for (int r = 0; r < 4; ++r) Rl[o + li][16 * c + 4 * r + g] = acc[r];
     }
+    __syncthreads();
+    // trailing update W_cd -= R_bc^T R_bd over the upper blocks b < c <= d
+    int p = 0;
+#pragma unroll 1
+    for (int cc = b + 1; cc < 4; ++cc)
+#pragma unroll 1
+      for (int dd = cc; dd < 4; ++dd, ++p) {
+        if ((p & 3) != wave) continue;
+        v4d acc = v4d{0, 0, 0, 0};
+        mma16(acc, lane, 1, [&](int i, int k) { return Rl[o + k][16 * cc + i]; },
+              [&](int k, int j) { return Rl[o + k][16 * dd + j]; });
 #pragma unroll
-    for (int q = 0; q < 15; ++q) {
-      c[q] = c[q + 1];
-      d[q] = d[q + 1];
+        for (int r = 0; r < 4; ++r) Rl[16 * cc + li][16 * dd + 4 * r + g] -= acc[r];
+      }
+    __syncthreads();
+  }
+  if (wave < 3) {
+    // block column bc = wave + 1 of T
+    const int bc = wave + 1;
+#pragma unroll 1
+    for (int a = bc - 1; a >= 0; --a) {
+      v4d acc = v4d{0, 0, 0, 0};
+#pragma unroll 1
+      for (int cb = a + 1; cb <= bc; ++cb)
+        mma16(acc, lane, 1, [&](int i, int k) { return Rl[16 * a + i][16 * cb + k]; },
+              [&](int k, int j) { return Tl[16 * cb + k][16 * bc + j]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tl[16 * a + li][16 * bc + 4 * r + g] = acc[r];
+      __builtin_amdgcn_wave_barrier();
+      v4d t = v4d{0, 0, 0, 0};
+      mma16(t, lane, 1, [&](int i, int k) { return Tl[16 * a + i][16 * a + k]; },
+            [&](int k, int j) { return Tl[16 * a + k][16 * bc + j]; });
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tl[16 * a + li][16 * bc + 4 * r + g] = -t[r];
     }
-    c[15] = 0.0;
-    d[15] = 0.0;
+  } else {
+    // the blocks below the diagonal of R and T are zero
+    for (int e = lane; e < 6 * 256; e += 64) {
+      const int blk = e >> 8, q = e & 255;
+      const int cb = blk < 3 ? 1 + blk : (blk < 5 ? 2 + (blk - 3) : 3);   // (1,0) (2,0) (3,0) (2,1) (3,1) (3,2)
+      const int db = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
+      Rl[16 * cb + (q & 15)][16 * db + (q >> 4)] = 0.0;
+      Tl[16 * cb + (q & 15)][16 * db + (q >> 4)] = 0.0;
+    }
   }
   __syncthreads();
 }
@@ -566,8 +621,7 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   __builtin_amdgcn_s_setprio(2);   // the panel chain sets the pace of the factorization
   __shared__ double Rl[kLeaf][kLeaf + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
-  __shared__ double rowW[2][kLeaf];
-  __shared__ double rowZ[2][kLeaf];
+  __shared__ double prow[16];
   __shared__ int s_exact, s_bad;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, w = a.w;
   if (tid == 0) { s_exact = (a.pass == 1); s_bad = 0; }
@@ -592,7 +646,7 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   __syncthreads();
   if (s_exact) {
     bool bad = false;
-    chol_aug(tid, rowW, rowZ, Rl, Tl, bad);
+    chol_blocked(tid, Rl, Tl, prow, bad);
     if (bad) s_bad = 1;
   } else {
     // W = I + E with |E| <= 1e-8: R = I + F, F = strict upper part of E plus
@@ -873,10 +927,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   typedef typename AccT<F32>::type Acc;
   __shared__ double sB[2][NK][64 + 1];
   const int split = blockIdx.y;
-  const NnTile t = nn_tile(a, blockIdx.x);
+  int tm = blockIdx.x / a.tilesN, tn = blockIdx.x % a.tilesN;
+  if (!SPLIT) xcd_tile(blockIdx.x, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
+  const NnTile t = nn_tile_at(a, tm, tn);
   const int kb = split * a.kchunk;
   const int ke = std::min(a.K, kb + a.kchunk);
   const int nfull = a.vec ? (ke - kb) / NK : 0;
+  // in-place update: C's loads go out before the products, so their latency
+  // overlaps the K loop instead of following it
+  double cval[16];
+  if (!SPLIT) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
+      cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+    }
+  }
   Acc acc[4];
 #pragma unroll
   for (int y = 0; y < 4; ++y) acc[y] = Acc{0, 0, 0, 0};
@@ -925,12 +991,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
       for (int r = 0; r < 4; ++r) mine[(y * 4 + r) * 64 + t.lane] = acc[y][r];
     return;
-  }
-  double cval[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
-    cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
   }
   if (!t.aok) return;
 #pragma unroll
