@@ -404,13 +404,6 @@ void launch_tn_reduce(const TnArgs& a, hipStream_t st) {
 // non-positive pivot sets info[0] = 1 + panel (first occurrence kept) and the
 // factorization continues with pivot 1.
 // --------------------------------------------------------------------------
-struct CholArgs {
-  const double* W; int64_t ldw;     // w x w Gram matrix
-  int w, pass, panel;
-  double* T; double* R1; double* Rout; int64_t ldr; int* info;
-  const double* X; int64_t ldx;     // pass 2, optional: w x w product P1^T Q_next
-  double* Rbar;                     // T^T X (ld ldr)
-};
 
 
 // 1/sqrt(x) to full double precision: hardware estimate plus one Newton step.
@@ -617,14 +610,16 @@ __device__ __forceinline__ void tmul_global_store(int tid, const double (*Tl)[kL
     }
 }
 
-__global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
-  __builtin_amdgcn_s_setprio(2);   // the panel chain sets the pace of the factorization
-  __shared__ double Rl[kLeaf][kLeaf + 1];
-  __shared__ double Tl[kLeaf][kLeaf + 1];
-  __shared__ double prow[16];
-  __shared__ int s_exact, s_bad;
+// The kernel body on caller-provided LDS (Rl, Tl: 64 x 65 each; prow: 16;
+// flags: 2 ints).  PASS1_ONLY drops the second-pass code.
+template <bool PASS1_ONLY>
+__device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1],
+                                          double* prow, int* flags) {
+  const int pass = PASS1_ONLY ? 1 : a.pass;
+  int& s_exact = flags[0];
+  int& s_bad = flags[1];
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, w = a.w;
-  if (tid == 0) { s_exact = (a.pass == 1); s_bad = 0; }
+  if (tid == 0) { s_exact = (pass == 1); s_bad = 0; }
   // W (w x w) into Rl, identity-padded: all loads issued first
   {
     double v[16];
@@ -641,7 +636,7 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
       far |= !(fabs(v[q] - (tx == k ? 1.0 : 0.0)) <= 1e-8);
     }
     __syncthreads();
-    if (a.pass == 2 && far) s_exact = 1;
+    if (pass == 2 && far) s_exact = 1;
   }
   __syncthreads();
   if (s_exact) {
@@ -673,10 +668,10 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
     const int k = ty + 4 * q;
     if (tx < w && k < w) {
       a.T[tx + k * w] = Tl[tx][k];
-      if (a.pass == 1) a.R1[tx + k * w] = Rl[tx][k];
+      if (pass == 1) a.R1[tx + k * w] = Rl[tx][k];
     }
   }
-  if (a.pass == 2) {
+  if (pass == 2) {
     // the next panel's update coefficients: (P1 T)^T Q_next = T^T X
     if (a.X) tmul_global_store(tid, Tl, a.X, a.ldx, w, a.Rbar, a.ldr);
     // R_panel = R2 R1 with R1 staged in Tl (T is stored)
@@ -692,13 +687,28 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   if (tid == 0 && s_bad && *a.info == 0) *a.info = 1 + a.panel;
 }
 
-void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st) {
+__global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
+  __builtin_amdgcn_s_setprio(2);   // the panel chain sets the pace of the factorization
+  __shared__ double Rl[kLeaf][kLeaf + 1];
+  __shared__ double Tl[kLeaf][kLeaf + 1];
+  __shared__ double prow[16];
+  __shared__ int flags[2];
+  chol_body<false>(a, Rl, Tl, prow, flags);
+}
+
+CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
+                   int64_t ldx, double* Rbar, int panel, const Scratch& s) {
   CholArgs c{};
   c.W = W; c.ldw = ldw;
   c.w = w; c.pass = pass; c.panel = panel;
   c.T = s.T; c.R1 = s.R1; c.Rout = Rout; c.ldr = ldr; c.info = s.info;
   c.X = X; c.ldx = ldx; c.Rbar = Rbar;
+  return c;
+}
+
+void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st) {
+  const CholArgs c = chol_args(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s);
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, c);
 }
 
@@ -922,13 +932,10 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
 // the block's K range is one split and its partial tile is stored for
 // nn_reduce_kernel; otherwise C is read at the end and updated in place.
 template <bool SPLIT, int TAG, bool F32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_kernel(NnArgs a) {
-  if (a.prio) __builtin_amdgcn_s_setprio(2);
+__device__ __forceinline__ void nn_body(const NnArgs& a, double (*sB)[NK][64 + 1], int bx, int split) {
   typedef typename AccT<F32>::type Acc;
-  __shared__ double sB[2][NK][64 + 1];
-  const int split = blockIdx.y;
-  int tm = blockIdx.x / a.tilesN, tn = blockIdx.x % a.tilesN;
-  if (!SPLIT) xcd_tile(blockIdx.x, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
+  int tm = bx / a.tilesN, tn = bx % a.tilesN;
+  if (!SPLIT) xcd_tile(bx, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
   const NnTile t = nn_tile_at(a, tm, tn);
   const int kb = split * a.kchunk;
   const int ke = std::min(a.K, kb + a.kchunk);
@@ -985,7 +992,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     __syncthreads();
   }
   if (SPLIT) {
-    double* mine = a.part + part_off(split, a.ntiles, blockIdx.x, t.wave);
+    double* mine = a.part + part_off(split, a.ntiles, bx, t.wave);
 #pragma unroll
     for (int y = 0; y < 4; ++y)
 #pragma unroll
@@ -1000,6 +1007,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
       const int j = t.jb + 16 * y + colsub(r, t.g, F32);
       if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
     }
+}
+
+template <bool SPLIT, int TAG, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ double sB[2][NK][64 + 1];
+  nn_body<SPLIT, TAG, F32>(a, sB, blockIdx.x, blockIdx.y);
+}
+
+// The re-projection update P -= Q S, split over K, with one extra block that
+// runs the panel's first Cholesky-QR pass: the factorization reads only the
+// Gram rows of the preceding product and the update only its coefficient
+// rows, so the single-block Cholesky runs alongside the update's blocks
+// instead of after them on the panel chain.  Block column x = ntiles holds the
+// Cholesky (its y > 0 blocks exit at once); both uses share the LDS layout
+// size (two 64 x 65 double arrays).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_chol_kernel(NnArgs a,
+                                                                                               CholArgs c) {
+  __builtin_amdgcn_s_setprio(2);
+  __shared__ double smem[2 * NK * (64 + 1)];
+  __shared__ double prow[16];
+  __shared__ int flags[2];
+  if ((int)blockIdx.x == a.ntiles) {
+    if (blockIdx.y == 0)
+      chol_body<true>(c, reinterpret_cast<double (*)[kLeaf + 1]>(smem),
+                      reinterpret_cast<double (*)[kLeaf + 1]>(smem + kLeaf * (kLeaf + 1)), prow, flags);
+    return;
+  }
+  nn_body<true, TAG_REPROJ, false>(a, reinterpret_cast<double (*)[NK][64 + 1]>(smem), blockIdx.x, blockIdx.y);
 }
 
 // C -= sum of the split partials (split order).  One block per wave of a
@@ -1075,6 +1111,12 @@ void launch_nn_product(const NnArgs& a, int tag, hipStream_t st) {
     case TAG_REPROJ: nn_launch_tag<TAG_REPROJ, false>(a, st); break;
     default: nn_launch_tag<TAG_PANEL, false>(a, st); break;
   }
+}
+
+bool launch_nn_chol(const NnArgs& a, const CholArgs& c, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0 || a.K <= NK || a.nsplit <= 1 || a.f32 || c.w > kLeaf) return false;
+  hipLaunchKernelGGL(nn_chol_kernel, dim3(a.ntiles + 1, a.nsplit), dim3(256), 0, st, a, c);
+  return true;
 }
 
 void launch_nn_reduce(const NnArgs& a, hipStream_t st) {

@@ -120,12 +120,30 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
 void launch_nn_product(const NnArgs& a, int tag, hipStream_t st);
 void launch_nn_reduce(const NnArgs& a, hipStream_t st);   // nsplit > 1 only
 
+// Arguments of the panel Cholesky kernel (Gram matrix W in, T = R^{-1} and R1
+// to scratch, on the second pass R2 R1 to Rout and T^T X to Rbar).
+struct CholArgs {
+  const double* W; int64_t ldw;     // w x w Gram matrix
+  int w, pass, panel;
+  double* T; double* R1; double* Rout; int64_t ldr; int* info;
+  const double* X; int64_t ldx;     // pass 2, optional: w x w product P1^T Q_next
+  double* Rbar;                     // T^T X (ld ldr)
+};
+
+CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
+                   int64_t ldx, double* Rbar, int panel, const Scratch& s);
+
 // Upper Cholesky factor of the panel Gram matrix W (w x w, ld ldw, w <= kLeaf).
 // pass 1: R1 <- chol(W), T <- R1^{-1}.  pass 2: R2 <- chol(W), T <- R2^{-1},
 // Rout (ldr) <- R2 R1, and, if X != nullptr, Rbar (ldr) <- T^T X (X: w x w,
 // ld ldx).  Breakdown sets info[0] = 1 + panel.
 void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
                  int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st);
+
+// The split re-projection update (launch_nn_product with nsplit > 1) with the
+// first Cholesky pass described by c run by one extra block of the same
+// launch; returns false, launching nothing, when the update does not split.
+bool launch_nn_chol(const NnArgs& a, const CholArgs& c, hipStream_t st);
 
 // P <- P T in place (T = s.T, w x w upper triangular), P is mrows x w.
 void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s, hipStream_t st);
