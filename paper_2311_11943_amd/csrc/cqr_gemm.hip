@@ -583,21 +583,28 @@ __device__ __forceinline__ void tmul_global_store(int tid, const double (*Tl)[kL
   v4d acc[4];
 #pragma unroll
   for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
-  for (int k0 = 0; k0 < 16 * wave + 16; k0 += 16) {
-    double xb[4][4];
+  // every k block the wave needs (k0 <= 16 wave) is requested before the
+  // first product, so the L2 round trips overlap
+  double xb[4][4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int k = k0 + 4 * g + s, j = 16 * y + li;
-        xb[y][s] = (k < w && j < w) ? X[k + (int64_t)j * ldx] : 0.0;
+        const int k = 16 * c + 4 * g + s, j = 16 * y + li;
+        xb[c][y][s] = (c <= wave && k < w && j < w) ? X[k + (int64_t)j * ldx] : 0.0;
       }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c > wave) break;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int k = k0 + 4 * g + s;
+      const int k = 16 * c + 4 * g + s;
       const double xa = Tl[k][16 * wave + li];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[y] = mfma(xb[y][s], xa, acc[y]);
+      for (int y = 0; y < 4; ++y) acc[y] = mfma(xb[c][y][s], xa, acc[y]);
     }
   }
   const int i = 16 * wave + li;
@@ -672,6 +679,13 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
     }
   }
   if (pass == 2) {
+    // R1 for R_panel = R2 R1, requested before T^T X so both loads overlap
+    double r1v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = ty + 4 * q;
+      r1v[q] = (tx < w && k < w) ? a.R1[tx + k * w] : (tx == k ? 1.0 : 0.0);
+    }
     // the next panel's update coefficients: (P1 T)^T Q_next = T^T X
     if (a.X) tmul_global_store(tid, Tl, a.X, a.ldx, w, a.Rbar, a.ldr);
     // R_panel = R2 R1 with R1 staged in Tl (T is stored)
@@ -679,7 +693,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = ty + 4 * q;
-      Tl[tx][k] = (tx < w && k < w) ? a.R1[tx + k * w] : (tx == k ? 1.0 : 0.0);
+      Tl[tx][k] = r1v[q];
     }
     __syncthreads();
     lds_mm_store<false, true>(tid, Rl, Tl, w, a.Rout, a.ldr);
