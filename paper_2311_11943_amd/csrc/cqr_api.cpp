@@ -347,22 +347,23 @@ void chol(cqr_plan_s& p, const double* W, int64_t ldw, int w, int pass, double* 
 
 // The split re-projection update C -= A B with the panel's first Cholesky
 // pass (c) run by one extra block of the same launch, then the split
-// reduction.  Returns false, launching nothing, when the update would not
-// split over K; the caller then runs the two steps separately.
+// reduction fused with the pass's transform C <- C T.  Returns false,
+// launching nothing, when the update would not split over K; the caller then
+// runs the update, the Cholesky and the transform separately.
 bool nn_chol(cqr_plan_s& p, double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb,
              int64_t M, int N, int K, const cqr::CholArgs& c, const cqr::Scratch& s, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= cqr::kLeaf || c.w > cqr::kLeaf) return false;
   cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, false);
   a.prio = 1;
-  if (a.nsplit <= 1) return false;
+  if (a.nsplit <= 1 || a.tilesN != 1 || N != c.w) return false;
   const double fl = 2.0 * M * N * (double)K + 2.0 * c.w * c.w * c.w;
   const double by = 8.0 * ((double)M * K + (double)K * N) + 24.0 * c.w * c.w;
   bool launched = false;
   prof(p, PH_REPROJ_NN, fl, by + partial_bytes(a.nsplit, a.ntiles), st,
        [&] { launched = cqr::launch_nn_chol(a, c, st); });
   if (!launched) return false;
-  prof(p, PH_REDUCE, (double)a.nsplit * M * N, partial_bytes(a.nsplit, a.ntiles) + 16.0 * (double)M * N, st,
-       [&] { cqr::launch_nn_reduce(a, st); });
+  prof(p, PH_REDUCE, (double)a.nsplit * M * N + 2.0 * M * N * N, partial_bytes(a.nsplit, a.ntiles) + 16.0 * (double)M * N,
+       st, [&] { cqr::launch_nn_reduce_apply(a, c.T, c.w, st); });
   return true;
 }
 
@@ -655,7 +656,8 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       if (p->cfg.reproject && k > 0) {
         // S = Q[:, :c0]^T P (rows < c0, also added into R[:c0, panel]);  P -= Q[:, :c0] S.
         // The first Cholesky pass needs only the Gram rows and the update only
-        // S, so when the update splits over K the Cholesky runs in its launch.
+        // S, so when the update splits over K the Cholesky runs in its launch
+        // and the transform P <- P R1^{-1} in its split reduction.
         tn(*p, PH_REPROJ_TN, Q, ldq, P, ldq, (int)c1, (int)b, mp, s.S, c1, R + c0 * ldr, ldr, s, st, (int)c0);
         W1 = s.S + c0;
         ldw1 = c1;
@@ -665,8 +667,10 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       } else {
         tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, (int)b, mp, s.G, b, nullptr, 0, s, st);
       }
-      if (!chol1) chol(*p, W1, ldw1, (int)b, 1, nullptr, 0, nullptr, 0, nullptr, k, s, st);
-      apply(*p, P, ldq, (int)b, s, st);
+      if (!chol1) {
+        chol(*p, W1, ldw1, (int)b, 1, nullptr, 0, nullptr, 0, nullptr, k, s, st);
+        apply(*p, P, ldq, (int)b, s, st);
+      }
       // Second pass.  With lookahead the same product also gives
       // X = P1^T Q_next, and the Cholesky kernel forms the next panel's
       // coefficients R[panel, next] = (P1 R2^{-1})^T Q_next = R2^{-T} X.

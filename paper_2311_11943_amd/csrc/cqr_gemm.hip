@@ -1079,6 +1079,66 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
   }
 }
 
+// The split reduction of a panel update (N = w <= 64 columns) followed by
+// the panel transform P <- P T (T: w x w, upper triangular): each block's 16 x
+// 64 strip of C - sum(partials) is staged in LDS and multiplied by T on MFMA
+// (wave q forms output columns 16q .. 16q + 15) before it is stored, so the
+// transform needs no launch or pass over P of its own.
+__global__ __launch_bounds__(256) void nn_reduce_apply_kernel(NnArgs a, const double* T, int w) {
+  __builtin_amdgcn_s_setprio(2);   // panel chain
+  __shared__ double sP[16][64 + 1];
+  __shared__ double sT[64][64 + 1];
+  const int tile = blockIdx.x >> 2, wave = blockIdx.x & 3;
+  const int qg = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int64_t i = (int64_t)tile * 64 + wave * 16 + li;
+  const bool aok = i < a.M;
+  const int64_t ic = aok ? i : 0;
+  double old[4], tv[16];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = 16 * qg + colsub(u, g, false);
+    old[u] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q, k = e & 63, j = e >> 6;
+    tv[q] = (k < w && j < w) ? T[k + j * w] : 0.0;
+  }
+  double v[4];
+  sum_partials4(a.part, a.nsplit, a.ntiles, tile, wave, qg, lane, v);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = 16 * qg + colsub(u, g, false);
+    sP[li][j] = j < w ? old[u] - v[u] : 0.0;   // columns past w hold clamped loads
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    sT[e & 63][e >> 6] = tv[q];
+  }
+  __syncthreads();
+  v4d acc = v4d{0, 0, 0, 0};
+#pragma unroll
+  for (int k0 = 0; k0 < 64; k0 += 16)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      acc = mfma(sT[k][16 * qg + li], sP[li][k], acc);
+    }
+  if (!aok) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = 16 * qg + 4 * r + g;
+    if (j < w) a.C[i + (int64_t)j * a.ldc] = acc[r];
+  }
+}
+
+bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, hipStream_t st) {
+  if (a.M <= 0 || a.nsplit <= 1 || a.tilesN != 1 || a.N != w || w > kLeaf || a.f32) return false;
+  hipLaunchKernelGGL(nn_reduce_apply_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w);
+  return true;
+}
+
 NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                 int N, int K, const Scratch& s, bool f32) {
   NnArgs a{};

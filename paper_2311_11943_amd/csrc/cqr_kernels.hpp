@@ -144,6 +144,10 @@ void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, in
 // first Cholesky pass described by c run by one extra block of the same
 // launch; returns false, launching nothing, when the update does not split.
 bool launch_nn_chol(const NnArgs& a, const CholArgs& c, hipStream_t st);
+// The split reduction of a panel update (a.N = w <= 64 columns, one column
+// tile) fused with the panel transform C <- C T (T: w x w, ld w); false,
+// launching nothing, for any other shape.
+bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, hipStream_t st);
 
 // P <- P T in place (T = s.T, w x w upper triangular), P is mrows x w.
 void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s, hipStream_t st);
