@@ -53,12 +53,12 @@ WORKLOADS = {
 # 64-wide dimension and a long reduction: 16 flop per byte, above the
 # 78.6 TFLOP/s / 8 TB/s ridge); the rest are bound by HBM bytes.
 MFMA_PHASES = {"reproj_product", "reproj_update", "panel_gram", "inpanel_projection", "trailing_product"}
-SINGLE_KERNEL_PHASES = ("trailing_product", "trailing_update", "reproj_product", "panel_gram", "panel_transform",
-                        "recover", "postorth")
+SINGLE_KERNEL_PHASES = ("trailing_product", "trailing_update", "reproj_product", "panel_gram", "recover",
+                        "postorth")
 KERNEL_OF = {
     "encode": "encode_rows_kernel / encode_cols_kernel",
     "reproj_product": "tn_lds_kernel<1, false>", "reproj_update": "nn_kernel<*, 1, false>",
-    "panel_gram": "tn_lds_kernel<2, false>", "panel_chol": "chol_kernel", "panel_transform": "apply_kernel",
+    "panel_gram": "tn_lds_kernel<2, false>", "panel_chol": "chol_kernel", "panel_transform": "apply_kernel / nn1_apply_kernel",
     "inpanel_projection": "tn/nn <2, false>",
     "trailing_product": "tn_lds_kernel<0, false>", "trailing_update": "nn1_kernel<0, false>",
     "split_reduce": "tn_reduce_kernel / nn_reduce_kernel", "recover": "line_kernel",

@@ -367,6 +367,20 @@ bool nn_chol(cqr_plan_s& p, double* C, int64_t ldc, const double* A, int64_t lda
   return true;
 }
 
+// The second pass's transform P <- P T (T = the pass's R^{-1} in scratch) and
+// the lookahead update C -= P B (B: w x w) in one launch; false, launching
+// nothing, when the shapes do not allow it.
+bool apply_update(cqr_plan_s& p, double* C, int64_t ldc, double* P, int64_t ldq, const double* B, int64_t ldb,
+                  int w, const cqr::Scratch& s, hipStream_t st) {
+  const int64_t mp = p.mp;
+  const cqr::NnArgs a = cqr::nn_setup(C, ldc, P, ldq, B, ldb, mp, w, w, s, false);
+  if (a.tilesN != 1 || a.K != w || w > cqr::kLeaf) return false;
+  bool launched = false;
+  prof(p, PH_APPLY, 4.0 * mp * w * w, 8.0 * (4.0 * mp * w + 2.0 * w * w), st,
+       [&] { launched = cqr::launch_nn1_apply(a, s.T, w, st); });
+  return launched;
+}
+
 void apply(cqr_plan_s& p, double* P, int64_t ldq, int w, const cqr::Scratch& s, hipStream_t st) {
   const int64_t mp = p.mp;
   prof(p, PH_APPLY, 2.0 * mp * w * w, 16.0 * mp * w, st, [&] { cqr::launch_apply(P, ldq, mp, w, s, st); });
@@ -679,10 +693,15 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, next ? 2 * (int)b : (int)b, mp, s.G, b, nullptr, 0, s, st);
       chol(*p, s.G, b, (int)b, 2, R + c0 + c0 * ldr, ldr, next ? s.G + b * b : nullptr, b,
            next ? R + c0 + c1 * ldr : nullptr, k, s, st);
-      apply(*p, P, ldq, (int)b, s, st);
+      // P <- P1 R2^{-1}, and with lookahead Q_next -= P R[panel, next] (one
+      // launch in FP64; the FP32 form keeps its FP32 update)
+      const bool fused = next && !f32 &&
+                         apply_update(*p, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, (int)b, s, st);
+      if (!fused) apply(*p, P, ldq, (int)b, s, st);
       if (next) {
-        // Q_next -= P R[panel, next]; the remaining columns on the side stream
-        nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st, f32);
+        // the remaining columns on the side stream
+        if (!fused)
+          nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st, f32);
         if (c1 + b < N)
           if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
       } else if (c1 < N) {

@@ -941,6 +941,74 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
     }
 }
 
+// The second pass's panel transform and the lookahead update in one launch:
+// P <- P1 T (T: w x w upper triangular, w = K <= 64), then C -= P B.  Each
+// block owns 64 rows of P and of C.  A lane's accumulators of the first
+// product hold P[i][4m + g] for m = 4y + r, which is exactly the operand the
+// lane supplies to the second product, so the transformed strip never leaves
+// the registers; it is also stored to P (the panel's final columns).
+__global__ __launch_bounds__(256) void nn1_apply_kernel(NnArgs a, const double* T, int w) {
+  __builtin_amdgcn_s_setprio(2);   // panel chain
+  __shared__ double sT[NK][64 + 1];
+  __shared__ double sB[NK][64 + 1];
+  const NnTile t = nn_tile(a, blockIdx.x);
+  double cval[16], xa[16], tv[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, false);
+    cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t.tid + 256 * q, k = e & 63, j = e >> 6;
+    tv[q] = (k < w && j < w) ? T[k + j * w] : 0.0;
+  }
+  // A = P1 (zero past K) in registers, the B slab into LDS
+  if (a.K == NK && a.vec) {
+    v2d rb[8];
+    nn_load_a(a, t, 0, xa);
+    nn_load_b(t, 0, rb);
+    __builtin_amdgcn_sched_barrier(0);
+    nn_put_b(sB, t, rb);
+  } else {
+    nn_load_tail(a, t, 0, a.K, xa, sB);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t.tid + 256 * q;
+    sT[e & 63][e >> 6] = tv[q];
+  }
+  __syncthreads();
+  v4d pf[4];
+#pragma unroll
+  for (int y = 0; y < 4; ++y) pf[y] = v4d{0, 0, 0, 0};
+  nn_mma(pf, sT, t, xa);
+#pragma unroll
+  for (int y = 0; y < 4; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) xa[4 * y + r] = pf[y][r];
+  v4d acc[4];
+#pragma unroll
+  for (int y = 0; y < 4; ++y) acc[y] = v4d{0, 0, 0, 0};
+  nn_mma(acc, sB, t, xa);
+  if (!t.aok) return;
+  double* P = const_cast<double*>(a.A);
+#pragma unroll
+  for (int y = 0; y < 4; ++y)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * y + 4 * r + t.g;
+      if (j < w) P[t.i + (int64_t)j * a.lda] = pf[y][r];
+      if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
+    }
+}
+
+bool launch_nn1_apply(const NnArgs& a, const double* T, int w, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0 || a.K != w || w > NK || a.tilesN != 1 || a.f32) return false;
+  hipLaunchKernelGGL(nn1_apply_kernel, dim3(a.ntiles), dim3(256), 0, st, a, T, w);
+  return true;
+}
+
 // Long K: slabs of 64 with the next slab's A and B loads in flight while the
 // current slab is multiplied (A register sets alternate explicitly).  SPLIT:
 // the block's K range is one split and its partial tile is stored for

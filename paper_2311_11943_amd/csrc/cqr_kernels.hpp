@@ -148,6 +148,10 @@ bool launch_nn_chol(const NnArgs& a, const CholArgs& c, hipStream_t st);
 // tile) fused with the panel transform C <- C T (T: w x w, ld w); false,
 // launching nothing, for any other shape.
 bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, hipStream_t st);
+// The panel transform A <- A T (A: M x w, the update's left operand; T: w x w,
+// ld w) and the rank-w update C -= A B in one launch (K = w <= 64, one column
+// tile, FP64); false, launching nothing, for any other shape.
+bool launch_nn1_apply(const NnArgs& a, const double* T, int w, hipStream_t st);
 
 // P <- P T in place (T = s.T, w x w upper triangular), P is mrows x w.
 void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s, hipStream_t st);
