@@ -43,6 +43,10 @@ listed with reasons in the design notes of the repository):
   * In-node placement: Q-checksum row k lives on grid row k mod p_r, R-checksum
     column k on grid column k mod p_c, corner blocks at their intersection.
   * Recovery uses the lowest-index surviving checksums.
+  * Without a horizontal code (K_h = 0, e.g. a p_r x 1 grid) R would be
+    unprotected; its p_r block rows then carry K_v checksum block rows of the
+    vertical code with G~_v, encoded at every panel boundary where failures
+    strike, and lost R blocks are decoded along block columns.
 """
 from __future__ import annotations
 
@@ -162,6 +166,11 @@ class Layout:
         self.hr = self.n // self.pr
         self.mp = self.m + self.kv * self.bs
         self.N = self.n + self.kh * self.bw
+        # Without a horizontal code (K_h = 0, e.g. p_c = 1) R is protected by a
+        # vertical code over its p_r block rows with the Q side's generator:
+        # K_v checksum block rows of height hr below R's n rows.
+        self.rcode = self.kh == 0 and self.kv > 0
+        self.rrows = self.n + (self.kv * self.hr if self.rcode else 0)
 
     def qblock(self, I: int, J: int):
         return (slice(I * self.bs, (I + 1) * self.bs), slice(J * self.bw, (J + 1) * self.bw))
@@ -181,13 +190,13 @@ class Layout:
         if self.storage == OUT_OF_NODE:
             assert 0 <= i < pr + self.kv and 0 <= j < pc + self.kh
             q = [(i, j)]
-            r = [(i, j)] if i < pr else []
+            r = [(i, j)] if (i < pr or self.rcode) else []
             return q, r
         assert 0 <= i < pr and 0 <= j < pc
         rows = [i] + [pr + k for k in range(self.kv) if k % pr == i]
         cols = [j] + [pc + k for k in range(self.kh) if k % pc == j]
         q = [(I, J) for I in rows for J in cols]
-        r = [(i, J) for J in cols]
+        r = [(I, J) for I in (rows if self.rcode else [i]) for J in cols]
         return q, r
 
 
@@ -374,12 +383,23 @@ def decode_line(blocks: list, checks: list, gen: np.ndarray, lost_data: list, lo
     return ghat
 
 
+def encode_r_rows(R: np.ndarray, gv: np.ndarray, lay: Layout):
+    """Without a horizontal code: R's checksum block rows (below its n rows)
+    are the vertical code of its p_r block rows, R_chk = (G~_v (x) I_hr) R[:n].
+    R entries become final only column block by column block (each panel's
+    re-projection adds into earlier rows), so the code is applied where
+    failures strike: at panel boundaries."""
+    if lay.rcode:
+        R[lay.n:] = kron_generator(gv, lay.hr) @ R[:lay.n]
+
+
 def recover(Q: np.ndarray, R: np.ndarray, nodes, lay: Layout, gv: np.ndarray, gh: np.ndarray):
     """Recover every block lost by `nodes` (erasure decoding, recovery lemma).
 
     Q is protected along each block column by the vertical code (Q_2 = G_v Q_1
     for every column, systematic and checksum); R along each block row by the
-    horizontal code (R_2 = R_1 G_h)."""
+    horizontal code (R_2 = R_1 G_h), or, without a horizontal code, along each
+    block column by the vertical code of encode_r_rows."""
     qset, rset = _erased_sets(nodes, lay)
     pr, pc = lay.pr, lay.pc
     for J in range(pc + lay.kh):
@@ -390,6 +410,16 @@ def recover(Q: np.ndarray, R: np.ndarray, nodes, lay: Layout, gv: np.ndarray, gh
         data = [Q[lay.qblock(I, J)] for I in range(pr)]
         chks = [Q[lay.qblock(pr + k, J)] for k in range(lay.kv)]
         decode_line(data, chks, gv, lost_d, lost_c)
+    if lay.rcode:
+        for J in range(pc):
+            lost_d = [I for I in range(pr) if (I, J) in rset]
+            lost_c = [k for k in range(lay.kv) if (pr + k, J) in rset]
+            if not lost_d and not lost_c:
+                continue
+            data = [R[lay.rblock(I, J)] for I in range(pr)]
+            chks = [R[lay.rblock(pr + k, J)] for k in range(lay.kv)]
+            decode_line(data, chks, gv, lost_d, lost_c)
+        rset = set()
     for i in range(pr):
         lost_d = [J for J in range(pc) if (i, J) in rset]
         lost_c = [k for k in range(lay.kh) if (i, pc + k) in rset]
@@ -487,22 +517,23 @@ def run(prob: Problem, snapshots: bool = False) -> dict:
     gh = r_generator(prob.gh_raw, lay.storage) if lay.kh else np.zeros((lay.pc, 0))
     At = encode(prob.A, gv, gh, lay)
     Q = At.copy()
-    R = np.zeros((lay.n, lay.N))
+    R = np.zeros((lay.rrows, lay.N))     # n rows, then R's checksum rows when lay.rcode
     npan = lay.n // opt.b
     events = dict((t, nodes) for t, nodes in prob.schedule)
     k = 0
     snaps = []
     for t in sorted(events) + [npan]:
-        factor_panels(Q, R, lay.n, k, t, opt)
+        factor_panels(Q, R[:lay.n], lay.n, k, t, opt)
         k = t
         if t == npan:
             break
+        encode_r_rows(R, gv, lay)
         before = (Q.copy(), R.copy()) if snapshots else None
         erase(Q, R, events[t], lay)
         recover(Q, R, events[t], lay, gv, gh)
         if snapshots:
             snaps.append((t, before[0], before[1], Q.copy(), R.copy()))
-    out = {"At": At, "Q": Q, "R": R, "gv": gv, "gh": gh, "snapshots": snaps}
+    out = {"At": At, "Q": Q, "R": R[:lay.n], "gv": gv, "gh": gh, "snapshots": snaps}
     if lay.kv:
         qp, bp = postorth(Q[:lay.m, :lay.n], prob.rhs, gv, lay.pr)
         out["Qpost"], out["bpost"] = qp, bp

@@ -362,6 +362,37 @@ def test_pipeline_with_failures_equals_failure_free(storage, K):
     np.testing.assert_allclose(x, np.linalg.solve(A, rhs), rtol=1e-9, atol=1e-10)
 
 
+@pytest.mark.parametrize("storage", [oc.OUT_OF_NODE, oc.IN_NODE])
+def test_r_row_code_recovers_without_horizontal_code(storage):
+    """p_c = 1 leaves R without a horizontal code; its block rows are then
+    protected by the vertical code with the Q side's generator.  Every set of
+    tolerated node failures (all pairs, checksum nodes included, out of node;
+    every single node in node, where f_tol = 1) at a mid panel must give the
+    failure-free factors."""
+    import itertools
+    m, n, pr, K, b = 256, 32, 8, 2, 8
+    lay = oc.Layout(m, n, pr, 1, K, 0, storage)
+    assert lay.rcode and lay.rrows == n + K * n // pr
+    A = synth.gaussian(m, n, 51)
+    v = synth.q_generator_draws(K, pr, 51)
+    opt = oc.FactorOptions(b, "cgs2")
+    base = oc.run(oc.Problem(A, lay, v, None, opt, []))
+    if storage == oc.OUT_OF_NODE:
+        nodes = [(i, 0) for i in range(pr + K)]
+        sets = list(itertools.combinations(nodes, 2))
+    else:
+        assert oc.f_tolerated(K, pr, storage) == 1
+        sets = [((i, 0),) for i in range(pr)]
+    for fail in sets:
+        out = oc.run(oc.Problem(A, lay, v, None, opt, [(2, list(fail))]))
+        assert np.abs(out["Q"] - base["Q"]).max() < 1e-12, fail
+        assert np.abs(out["R"] - base["R"]).max() < 1e-12 * np.abs(base["R"]).max(), fail
+    # one more than tolerated on the code line cannot be decoded
+    with pytest.raises(oc.NotRecoverable):
+        over = [(i, 0) for i in range(K + 1)] if storage == oc.OUT_OF_NODE else [(0, 0), (1, 0)]
+        oc.run(oc.Problem(A, lay, v, None, opt, [(2, over)]))
+
+
 def test_tall_coded_solve_is_weighted_least_squares():
     """For tall A the post-orthogonalized solve x = R_1^{-1} (G_0 Q_1)^T (G_0 b)
     minimises (Ax - b)^T W (Ax - b) with W = I + G_v^T G_v: closed form
