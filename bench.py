@@ -237,6 +237,8 @@ def run_adjoint(args):
     dev = torch.device("cuda:0")
     m, n, pr, K, b = 65536, 512, 16, 2, 64
     cfg = cqr.Config(m, n, pr, 1, K, 0, b, cqr.CQR_OUT_OF_NODE)
+    # two nodes fail at once at a random panel (R is protected by its checksum rows)
+    sched = synth.draw_schedule("burst", n // b, pr, 1, args.seed, nfail=2)
     v = synth.q_generator_draws(K, pr, args.seed)
     engine = cqr.CodedQR(cfg, v, None, dev)
     A = torch.tensor(synth.gaussian(m, n, args.seed), device=dev, requires_grad=True)
@@ -244,7 +246,7 @@ def run_adjoint(args):
     xt = torch.tensor(synth.gaussian(n, 1, args.seed + 2), device=dev)
 
     def fwd():
-        Q, R1 = ag.coded_qr(A, engine)
+        Q, R1 = ag.coded_qr(A, engine, sched)
         return ag.coded_solve(Q, R1, B, engine)
 
     def ev():
@@ -294,13 +296,84 @@ def run_adjoint(args):
         "higher_is_better": False, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "c4: m=65536, n=512 Gaussian A and b, 16x1 grid (4096-row blocks), b=64, "
-                               "K_v=2 out-of-node, no horizontal code, failure free",
-                   "m": m, "n": n, "grid": "16x1", "b": b, "K_v": K},
+                               "K_v=2 out-of-node, no horizontal code (R protected by its checksum rows), "
+                               "2 nodes failing at once at a random panel",
+                   "m": m, "n": n, "grid": "16x1", "b": b, "K_v": K,
+                   "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched]},
         "forward_ms": round(fm, 4), "backward_ms": round(bm, 4),
         "forward_tflops": round(f_fl / (fm * 1e-3) / 1e12, 3), "backward_tflops": round(b_fl / (bm * 1e-3) / 1e12, 3),
         "errors": {"x_vs_weighted_ls": relx, "dA_vs_closed_form": relA, "db_vs_closed_form": relB},
     }), flush=True)
     engine.close()
+
+
+def _submatrix_extremes(task):
+    """Smallest |det| and largest 2-norm condition number over the k x k
+    submatrices of G with row set `rows` and column sets starting at column c0."""
+    import itertools
+    G, k, rows, c0 = task
+    p = G.shape[1]
+    mind, maxc = np.inf, 0.0
+    rest = itertools.combinations(range(c0 + 1, p), k - 1)
+    while True:
+        chunk = list(itertools.islice(rest, 200000))
+        if not chunk and k > 1:
+            break
+        cols = np.array([(c0,) + c for c in chunk], dtype=np.int64) if k > 1 else np.array([[c0]])
+        sub = G[np.ix_(rows, range(p))][:, cols].transpose(1, 0, 2)      # (N, k, k)
+        mind = min(mind, float(np.abs(np.linalg.det(sub)).min()))
+        sv = np.linalg.svd(sub, compute_uv=False)
+        maxc = max(maxc, float((sv[:, 0] / sv[:, -1]).max()))
+        if k == 1:
+            break
+    return mind, maxc
+
+
+def run_generator_study(args):
+    """The paper's check of its Q-side generator (the experiment behind its
+    figure comparing structured and random generators): smallest |det| and
+    largest condition number over all square submatrices of the structured
+    G~ = [G~_1  V~] (G~_1 = -1/2 V~ V~^T, as the library builds it) and of the
+    completely random G~' = [G~_1'  V~] (G~_1' i.i.d. Unif(0, 1), same V~), for
+    f = 2..6 checksum rows and p_r = 16, 32, 64 grid rows, averaged (in log10)
+    over trials.  Host only (the generator comes from the library's plan), one
+    JSON line per (p_r, f)."""
+    import itertools
+    import multiprocessing as mp
+    from paper_2311_11943_amd import cqr
+    trials = {(16, f): 100 for f in range(2, 7)}
+    trials.update({(32, 2): 100, (32, 3): 100, (32, 4): 100, (32, 5): 20, (32, 6): 5})
+    trials.update({(64, 2): 100, (64, 3): 20, (64, 4): 5, (64, 5): 2, (64, 6): 1})
+    scale = args.study_scale
+    with mp.Pool(args.study_procs) as pool:
+        for pr in (16, 32, 64):
+            for f in range(2, 7):
+                nt = max(1, int(round(trials[(pr, f)] * scale)))
+                logs = {"structured": [], "random": []}
+                t0 = time.perf_counter()
+                for t in range(nt):
+                    v = synth.q_generator_draws(f, pr, 1000 + t)
+                    cfg = cqr.Config(m=16 * pr, n=16 * pr, pr=pr, pc=1, kv=f, kh=0, b=16)
+                    plan = cqr.coded_qr_plan_create(cfg, v, None)
+                    gv, _ = cqr.coded_qr_plan_generators(plan, cfg)
+                    cqr.coded_qr_plan_destroy(plan)
+                    rng = np.random.default_rng(5000 + t)
+                    gr = gv.copy()
+                    gr[:, :f] = rng.uniform(0.0, 1.0, (f, f))
+                    for name, G in (("structured", gv), ("random", gr)):
+                        tasks = [(G, k, list(rows), c0) for k in range(1, f + 1)
+                                 for rows in itertools.combinations(range(f), k) for c0 in range(pr - k + 1)]
+                        res = pool.map(_submatrix_extremes, tasks, chunksize=4)
+                        logs[name].append((np.log10(min(r[0] for r in res)), np.log10(max(r[1] for r in res))))
+                out = {"study": "generator submatrix conditioning", "p_r": pr, "f": f, "trials": nt,
+                       "seconds": round(time.perf_counter() - t0, 1)}
+                for name, vals in logs.items():
+                    a = np.array(vals)
+                    out[name] = {"log10_min_abs_det": round(float(a[:, 0].mean()), 3),
+                                 "log10_max_cond": round(float(a[:, 1].mean()), 3)}
+                out["max_cond_ratio_structured_over_random"] = round(
+                    10 ** (out["structured"]["log10_max_cond"] - out["random"]["log10_max_cond"]), 3)
+                print(json.dumps(out), flush=True)
 
 
 def main():
@@ -330,6 +403,11 @@ def main():
                     help="instead of the benchmark line: forward + adjoint of the tall-skinny least-squares "
                          "workload (m = 65536, n = 512), one JSON line")
     ap.add_argument("--reps", type=int, default=5, help="repetitions of each timed extra (overhead legs)")
+    ap.add_argument("--generator-study", action="store_true",
+                    help="host only: smallest |det| and largest condition number over all square submatrices of "
+                         "the structured and of a random Q-side generator (f = 2..6, p_r = 16, 32, 64)")
+    ap.add_argument("--study-scale", type=float, default=1.0, help="scales the study's trial counts")
+    ap.add_argument("--study-procs", type=int, default=min(8, os.cpu_count() or 1))
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -337,6 +415,9 @@ def main():
               "(the processor grid is simulated as blocks of one matrix); --gpus must be 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.generator_study:
+        run_generator_study(args)
+        return
     if args.sweep:
         run_sweep(args)
         return

@@ -21,7 +21,10 @@
  *
  * Shapes: A is m x n (m >= n), p_r | m, p_c | n, p_r | n.  Block height
  * bs = m/p_r, block width bw = n/p_c, R block height hr = n/p_r.  The encoded
- * matrix A~ has m' = m + K_v*bs rows and N = n + K_h*bw columns; R is n x N.
+ * matrix A~ has m' = m + K_v*bs rows and N = n + K_h*bw columns; R is
+ * r_rows x N (coded_qr_plan_r_rows): n rows, plus, when the plan has no
+ * horizontal code (K_h = 0, K_v > 0, e.g. a p_r x 1 grid), K_v*hr checksum rows
+ * that protect R's block rows with the vertical code (below R_1's n rows).
  */
 #ifndef CQR_H
 #define CQR_H
@@ -108,6 +111,15 @@ cqr_status coded_qr_plan_generators(cqr_plan plan, double* gv, double* gh);
  * minimum in-node checksum count). */
 int32_t coded_qr_plan_ftol(cqr_plan plan);
 
+/* Rows of R: n, or n + K_v*hr when K_h = 0 and K_v > 0.  Without R-checksum
+ * columns, a failed node's R blocks would have no code; R's p_r block rows
+ * then carry K_v checksum block rows R_chk = (G~_v (x) I_hr) R[0:n], written
+ * by coded_qr_factor at the end of every call (the panel boundaries where
+ * failures strike; R's entries become final only column block by column
+ * block, since each panel's re-projection adds into earlier rows) and decoded
+ * along block columns by coded_qr_recover. */
+int64_t coded_qr_plan_r_rows(cqr_plan plan);
+
 /* Bytes of device workspace coded_qr_factor needs (caller allocates). */
 size_t coded_qr_workspace_bytes(cqr_plan plan);
 
@@ -130,7 +142,8 @@ cqr_status coded_qr_encode(cqr_plan plan, double* At, int64_t ldat, hipStream_t 
  *   trailing update over every column right of the panel, checksum columns
  *     included:  R_bar = Qbar^T Q_t,  R[panel, right] = R_bar,  Q_t -= Qbar R_bar.
  * At (device, m' x N, ldat): the iteration state Q^(t) (A~ on the first call);
- * R (device, n x N, ldr): zeroed by this call when panel_begin == 0.
+ * R (device, r_rows x N, ldr >= r_rows): rows [0, n) zeroed by this call when
+ * panel_begin == 0; R's checksum rows (if any) re-encoded before it returns.
  * ws (device, >= coded_qr_workspace_bytes bytes, 256-byte aligned).
  * Calls may be split at any panel boundary (failures are injected between).
  * Numerical breakdown (rank deficiency) is recorded in the workspace and read
@@ -151,7 +164,9 @@ cqr_status coded_qr_ws_info(cqr_plan plan, const void* ws, hipStream_t stream, i
  * storage: 0 <= i < p_r + K_v, 0 <= j < p_c + K_h (i >= p_r or j >= p_c name
  * checksum nodes).  In-node: 0 <= i < p_r, 0 <= j < p_c; a node also holds the
  * checksum blocks placed on it (Q-checksum row k on grid row k mod p_r,
- * R-checksum column k on grid column k mod p_c).
+ * R-checksum column k on grid column k mod p_c).  With R checksum rows
+ * (coded_qr_plan_r_rows > n) R-checksum block row k sits with Q-checksum row k.
+ * ldq >= m', ldr >= r_rows.
  */
 cqr_status coded_qr_erase(cqr_plan plan, double* Q, int64_t ldq, double* R, int64_t ldr,
                           const int32_t* failed_ij, int32_t nfailed, hipStream_t stream);
@@ -160,8 +175,9 @@ cqr_status coded_qr_erase(cqr_plan plan, double* Q, int64_t ldq, double* R, int6
  * Recover every block held by the listed nodes from surviving blocks and
  * checksums (recovery-overhead lemma, decoding equation): per affected block
  * column of Q (vertical code, Q_2 = G_v Q_1 holds for all N columns) and per
- * block row of R (horizontal code, R_2 = R_1 G_h), with F the erased data
- * blocks and S the |F| lowest-index surviving checksums,
+ * block row of R (horizontal code, R_2 = R_1 G_h; without one, per block
+ * column of R with its checksum rows and G_v), with F the erased data blocks
+ * and S the |F| lowest-index surviving checksums,
  *   X_F = G_hat^{-1} (C_S - sum_{t not in F} g~_{S,t} X_t),   G_hat = G~[S, F],
  * then lost checksum blocks are re-encoded.  The small solve runs on the host
  * in FP64 (no device read-back); every output block is one linear combination

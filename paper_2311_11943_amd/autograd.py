@@ -42,7 +42,7 @@ class CodedQRFunction(torch.autograd.Function):
                 break
             engine.erase(At, R, nodes)
             engine.recover(At, R, nodes)
-        Q, R1 = At[:, :c.n], R[:, :c.n]
+        Q, R1 = At[:, :c.n], R[:c.n, :c.n]
         ctx.engine = engine
         ctx.save_for_backward(Q, R1)
         return Q, R1

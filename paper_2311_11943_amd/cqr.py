@@ -26,7 +26,7 @@ EXPORTS = [
     "coded_qr_erase", "coded_qr_recover", "coded_qr_postorth", "coded_qr_status_string",
     "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name", "coded_qr_solve",
     "coded_qr_solve_workspace_bytes", "coded_qr_backward", "coded_qr_backward_workspace_bytes",
-    "coded_qr_solve_backward", "coded_qr_solve_backward_workspace_bytes",
+    "coded_qr_solve_backward", "coded_qr_solve_backward_workspace_bytes", "coded_qr_plan_r_rows",
 ]
 
 PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram", "panel_chol", "panel_transform",
@@ -75,6 +75,7 @@ def _load() -> ctypes.CDLL:
         "coded_qr_solve": (I32, [P, D, I64, D, I64, D, I64, I32, D, I64, V, ctypes.c_size_t, V]),
         "coded_qr_solve_workspace_bytes": (ctypes.c_size_t, [P, I32]),
         "coded_qr_backward_workspace_bytes": (ctypes.c_size_t, [P]),
+        "coded_qr_plan_r_rows": (I64, [P]),
         "coded_qr_backward": (I32, [P, D, I64, D, I64, D, I64, D, I64, D, I64, V, ctypes.c_size_t, V]),
         "coded_qr_solve_backward_workspace_bytes": (ctypes.c_size_t, [P, I32]),
         "coded_qr_solve_backward": (I32, [P, D, I64, D, I64, D, I64, D, I64, D, I64, I32, D, I64, D, I64, D, I64,
@@ -271,6 +272,10 @@ def coded_qr_solve(plan: int, Qpost, R, Bpost, X, ws, stream=None) -> int:
                               ws.numel() * ws.element_size(), ctypes.c_void_p(_stream(stream)))
 
 
+def coded_qr_plan_r_rows(plan: int) -> int:
+    return LIB.coded_qr_plan_r_rows(ctypes.c_void_p(plan))
+
+
 def coded_qr_backward_workspace_bytes(plan: int) -> int:
     return LIB.coded_qr_backward_workspace_bytes(ctypes.c_void_p(plan))
 
@@ -340,10 +345,14 @@ class CodedQR:
     def generators(self):
         return coded_qr_plan_generators(self.plan, self.cfg)
 
+    @property
+    def r_rows(self) -> int:
+        return coded_qr_plan_r_rows(self.plan)
+
     def alloc(self):
-        """Column-major A~ (m' x N) and R (n x N) buffers."""
+        """Column-major A~ (m' x N) and R (r_rows x N) buffers; R_1 is R[:n, :n]."""
         c = self.cfg
-        return col_major(c.mp, c.N, self.device), col_major(c.n, c.N, self.device)
+        return col_major(c.mp, c.N, self.device), col_major(self.r_rows, c.N, self.device)
 
     def encode(self, At):
         _check(coded_qr_encode(self.plan, At), "coded_qr_encode")

@@ -25,6 +25,10 @@ using cqr::kTile;
 struct cqr_plan_s {
   cqr_config cfg;
   int64_t bs, bw, hr, mp, N;
+  // no horizontal code (K_h = 0, K_v > 0): R carries K_v checksum block rows
+  // of the vertical code below its n rows, so R has rrows rows
+  bool rcode = false;
+  int64_t rrows = 0;
   int ftol;
   std::vector<double> gv;   // K_v x p_r row-major:  [G~_1  V~]
   std::vector<double> gh;   // p_c x K_h row-major
@@ -102,19 +106,25 @@ bool invert(std::vector<double> a, int n, std::vector<double>& inv) {
 
 // Blocks a failed node holds.  Q blocks are (I, J) on the (p_r+K_v) x (p_c+K_h)
 // block grid of A~; R blocks are (i, J) with i < p_r.
+// Blocks a node holds: Q blocks (I, J) of bs x bw, R blocks (i, J) of hr x bw
+// (block rows i >= p_r are R's checksum rows when the plan has the R row code).
 void node_blocks(const cqr_plan_s& p, int i, int j, std::vector<std::pair<int, int>>& q,
                  std::vector<std::pair<int, int>>& r) {
   const int pr = p.cfg.pr, pc = p.cfg.pc, kv = p.cfg.kv, kh = p.cfg.kh;
   if (p.cfg.storage == CQR_OUT_OF_NODE) {
     q.push_back({i, j});
-    if (i < pr) r.push_back({i, j});
+    if (i < pr || p.rcode) r.push_back({i, j});
     return;
   }
   std::vector<int> rows{i}, cols{j};
   for (int k = 0; k < kv; ++k) if (k % pr == i) rows.push_back(pr + k);
   for (int k = 0; k < kh; ++k) if (k % pc == j) cols.push_back(pc + k);
   for (int I : rows) for (int J : cols) q.push_back({I, J});
-  for (int J : cols) r.push_back({i, J});
+  if (p.rcode) {
+    for (int I : rows) for (int J : cols) r.push_back({I, J});
+  } else {
+    for (int J : cols) r.push_back({i, J});
+  }
 }
 
 cqr_status check_nodes(const cqr_plan_s& p, const int32_t* ij, int32_t nf) {
@@ -463,6 +473,8 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   p->bw = c.n / c.pc;
   p->hr = c.n / c.pr;
   p->mp = c.m + c.kv * p->bs;
+  p->rcode = c.kh == 0 && c.kv > 0;
+  p->rrows = c.n + (p->rcode ? (int64_t)c.kv * p->hr : 0);
   p->N = c.n + c.kh * p->bw;
 
   // Q-side generator: G~_v = [G~_1  V~],  G~_1 = -1/2 V~ V~^T.
@@ -555,6 +567,8 @@ cqr_status coded_qr_plan_generators(cqr_plan p, double* gv, double* gh) {
 
 int32_t coded_qr_plan_ftol(cqr_plan p) { return p ? p->ftol : -1; }
 
+int64_t coded_qr_plan_r_rows(cqr_plan p) { return p ? p->rrows : 0; }
+
 size_t coded_qr_workspace_bytes(cqr_plan p) { return p ? p->ws_bytes : 0; }
 
 cqr_status coded_qr_encode(cqr_plan p, double* At, int64_t ldat, hipStream_t st) {
@@ -587,7 +601,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
   if (!p || !Q || !R || !ws) return CQR_EINVAL;
   const int64_t n = p->cfg.n, b = p->cfg.b, N = p->N, mp = p->mp;
   const int npan = (int)(n / b);
-  if (ldq < mp || ldr < n || pb < 0 || pe > npan || pb > pe) return CQR_EINVAL;
+  if (ldq < mp || ldr < p->rrows || pb < 0 || pe > npan || pb > pe) return CQR_EINVAL;
   if (ws_bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255)) return CQR_ENOMEM;
   cqr::Scratch s = scratch_of(*p, ws);
   const cqr::Scratch s2 = scratch_of(*p, ws, true);
@@ -732,6 +746,19 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     if (e == hipSuccess) e = hipStreamWaitEvent(caller, p->ev_chain, 0);
     if (e != hipSuccess) return hip_fail(e);
   }
+  if (p->rcode) {
+    // R's checksum rows: the vertical code of its block rows, encoded at the
+    // panel boundary where this call ends (where failures are injected); R's
+    // entries become final only column block by column block, because each
+    // panel's re-projection adds into earlier rows
+    cqr::EncodeArgs a{};
+    a.At = R; a.ld = ldr;
+    a.m = n; a.n = N; a.bs = p->hr; a.bw = p->bw;
+    a.pr = p->cfg.pr; a.pc = p->cfg.pc; a.kv = p->cfg.kv; a.kh = 0;
+    for (size_t e = 0; e < p->gv.size(); ++e) a.g[e] = p->gv[e];
+    const double c = (double)a.kv * a.bs;
+    prof(*p, PH_ENCODE, 2.0 * c * a.pr * N, 8.0 * (n + c) * N, caller, [&] { cqr::launch_encode_rows(a, caller); });
+  }
   return hip_status();
 }
 
@@ -749,7 +776,7 @@ cqr_status coded_qr_ws_info(cqr_plan p, const void* ws, hipStream_t st, int32_t*
 cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,
                           int32_t nf, hipStream_t st) {
   drop_pending_error();
-  if (!p || !Q || !R || ldq < p->mp || ldr < p->cfg.n) return CQR_EINVAL;
+  if (!p || !Q || !R || ldq < p->mp || ldr < p->rrows) return CQR_EINVAL;
   cqr_status cs = check_nodes(*p, ij, nf);
   if (cs != CQR_OK) return cs;
   std::set<std::pair<int, int>> qs, rs;
@@ -779,7 +806,7 @@ cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t
 cqr_status coded_qr_recover(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,
                             int32_t nf, hipStream_t st) {
   drop_pending_error();
-  if (!p || !Q || !R || ldq < p->mp || ldr < p->cfg.n) return CQR_EINVAL;
+  if (!p || !Q || !R || ldq < p->mp || ldr < p->rrows) return CQR_EINVAL;
   cqr_status cs = check_nodes(*p, ij, nf);
   if (cs != CQR_OK) return cs;
   const int pr = p->cfg.pr, pc = p->cfg.pc, kv = p->cfg.kv, kh = p->cfg.kh;
@@ -816,8 +843,36 @@ cqr_status coded_qr_recover(cqr_plan p, double* Q, int64_t ldq, double* R, int64
       launches.push_back(a);
     }
   }
+  // R without a horizontal code: every block column J, the vertical code of
+  // R's block rows (the same generator as Q's).
+  if (p->rcode && !rs.empty()) {
+    for (int J = 0; J < pc; ++J) {
+      LineJob job;
+      for (int I = 0; I < pr; ++I) if (rs.count({I, J})) job.lost_d.push_back(I);
+      for (int k = 0; k < kv; ++k) if (rs.count({pr + k, J})) job.lost_c.push_back(k);
+      if (job.lost_d.empty() && job.lost_c.empty()) continue;
+      std::vector<int> srcs, outs;
+      std::vector<double> coef;
+      cs = plan_line(p->gv, pr, kv, job, srcs, outs, coef);
+      if (cs != CQR_OK) return cs;
+      auto off = [&](int slot) { return (int64_t)slot * p->hr + (int64_t)J * p->bw * ldr; };
+      const int ns = (int)srcs.size();
+      for (size_t o0 = 0; o0 < outs.size(); o0 += kMaxOut) {
+        cqr::LineArgs a{};
+        a.base = R; a.ld = ldr; a.rows = (int)p->hr; a.cols = (int)p->bw;
+        a.nsrc = ns;
+        a.nout = (int)std::min<size_t>(kMaxOut, outs.size() - o0);
+        for (int s = 0; s < ns; ++s) a.src[s] = off(srcs[s]);
+        for (int o = 0; o < a.nout; ++o) {
+          a.dst[o] = off(outs[o0 + o]);
+          for (int s = 0; s < ns; ++s) a.coef[o][s] = coef[(o0 + o) * ns + s];
+        }
+        launches.push_back(a);
+      }
+    }
+  }
   // R: every block row i, horizontal code  chk_k = sum_t g~_h[t][k] data_t.
-  if (!rs.empty()) {
+  if (!rs.empty() && !p->rcode) {
     std::vector<double> genT((size_t)kh * pc);
     for (int k = 0; k < kh; ++k)
       for (int t = 0; t < pc; ++t) genT[(size_t)k * pc + t] = p->gh[t * kh + k];

@@ -108,6 +108,21 @@ def test_plan_accepts_fp32_trailing_precision():
     cqr.coded_qr_plan_destroy(p)
 
 
+def test_r_rows_with_and_without_horizontal_code():
+    cfg = cqr.Config(m=1024, n=128, pr=8, pc=1, kv=2, kh=0, b=32)
+    p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(2, 8, 1), None)
+    try:
+        assert cqr.coded_qr_plan_r_rows(p) == 128 + 2 * 128 // 8
+    finally:
+        cqr.coded_qr_plan_destroy(p)
+    cfg = cqr.Config(m=256, n=256, pr=4, pc=4, kv=1, kh=1, b=16)
+    p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(1, 4, 1), synth.r_generator_draws(4, 1, 1))
+    try:
+        assert cqr.coded_qr_plan_r_rows(p) == 256
+    finally:
+        cqr.coded_qr_plan_destroy(p)
+
+
 def test_solve_workspace_size():
     cfg = cqr.Config(m=240, n=240, pr=4, pc=4, kv=1, kh=1, b=16)
     p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(1, 4, 1), synth.r_generator_draws(4, 1, 1))

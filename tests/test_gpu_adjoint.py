@@ -2,10 +2,9 @@
 
 - coded_qr_backward and coded_qr_solve_backward against the adjoint oracle on
   the same factors and cotangents (1e-10 relative to the largest entry);
-- the torch.autograd functions end to end (forward with a failure schedule on
-  the square grid, backward through the solve and the QR) against the
-  closed-form gradient of the W-weighted least-squares solution (1e-8
-  relative);
+- the torch.autograd functions end to end (forward with a failure schedule,
+  backward through the solve and the QR) against the closed-form gradient of
+  the W-weighted least-squares solution (1e-8 relative);
 - torch.autograd.gradcheck (central differences through the GPU forward) on a
   small problem.
 """
@@ -76,11 +75,10 @@ def test_autograd_matches_weighted_least_squares_gradient(mods, kind):
         b = 32
         sched = synth.draw_schedule("random", lay.n // b, lay.pr, lay.pc, 34, nfail=2)
     else:
-        # a p_c = 1 grid has no horizontal code, so a failed node's R blocks
-        # cannot be decoded: the tall case runs failure free
+        # p_c = 1: no horizontal code, R's checksum rows protect it; two nodes at once
         A, v, gh, lay = make_inputs(128, 8, 2, 32, "out", seed=34, m=1024, pc=1, kh=0)
         b = 32
-        sched = []
+        sched = [(2, [(1, 0), (6, 0)])]
     print(f"[case] autograd {kind}, schedule {sched}", flush=True)
     Bh = synth.gaussian(lay.m, 1, 35)
     xt = synth.gaussian(lay.n, 1, 36)

@@ -120,6 +120,45 @@ def test_failures_recover_to_snapshot_and_final_matches(cqr, sid, n, pr, K, b, s
     q.close()
 
 
+@pytest.mark.parametrize("storage", ["out", "in"])
+def test_failures_without_horizontal_code(cqr, storage):
+    """An 8 x 1 grid has no R-checksum columns: R's checksum rows (the vertical
+    code of its block rows) decode a failed node's R block row.  Out of node:
+    two nodes at once, then a data and a checksum node; in node (f_tol = 1):
+    one node per event."""
+    n, pr, K, b, m = 128, 8, 2, 32, 1024
+    A, v, gh, lay = make_inputs(n, pr, K, b, storage, seed=4, m=m, pc=1, kh=0)
+    print(f"[case] no horizontal code, {storage} of node", flush=True)
+    q = cqr.CodedQR(gpu_config(cqr, lay, b), v, gh)
+    assert lay.rcode and q.r_rows == lay.rrows
+    sched = [(1, [(1, 0), (5, 0)]), (3, [(2, 0), (pr + 1, 0)])] if storage == "out" else \
+            [(1, [(3, 0)]), (3, [(1, 0)])]
+    At, R = q.alloc()
+    At[:lay.m, :lay.n].copy_(_dev(cqr, A))
+    q.encode(At)
+    k = 0
+    for t, nodes in sched:
+        q.factor(At, R, k, t)
+        k = t
+        before_Q, before_R = host(At), host(R)
+        q.erase(At, R, nodes)
+        torch.cuda.synchronize()
+        erased_R = np.isnan(host(R))
+        assert erased_R.any()
+        q.recover(At, R, nodes)
+        torch.cuda.synchronize()
+        Qg, Rg = host(At), host(R)
+        assert not np.isnan(Qg).any() and not np.isnan(Rg).any()
+        assert rel(Qg, before_Q) < 1e-10
+        assert np.abs(Rg - before_R).max() <= 1e-10 * np.abs(before_R).max()
+    q.factor(At, R, k, n // b)
+    out = oc.run(oc.Problem(A, lay, v, gh, oc.FactorOptions(b, "icgs"), sched))
+    Qg, Rg = host(At), host(R)
+    q.close()
+    assert rel(Rg[:n], out["R"]) < 1e-11
+    assert np.abs(Qg - out["Q"]).max() < 1e-11
+
+
 @pytest.mark.parametrize("sid,n,pr,K,b", [("innode", 512, 8, 2, 64), ("ragged", 240, 4, 1, 16)])
 def test_lookahead_matches_single_stream(cqr, sid, n, pr, K, b):
     """The second-stream schedule runs the same operations; only split-product
