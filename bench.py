@@ -333,11 +333,11 @@ def run_generator_study(args):
     """The paper's check of its Q-side generator (the experiment behind its
     figure comparing structured and random generators): smallest |det| and
     largest condition number over all square submatrices of the structured
-    G~ = [G~_1  V~] (G~_1 = -1/2 V~ V~^T, as the library builds it) and of the
+    G~ = [G~_1  V~] (G~_1 = -1/2 V~ V~^T; checked against the library's plan
+    generator wherever a plan can hold the grid) and of the
     completely random G~' = [G~_1'  V~] (G~_1' i.i.d. Unif(0, 1), same V~), for
     f = 2..6 checksum rows and p_r = 16, 32, 64 grid rows, averaged (in log10)
-    over trials.  Host only (the generator comes from the library's plan), one
-    JSON line per (p_r, f)."""
+    over trials.  Host only, one JSON line per (p_r, f)."""
     import itertools
     import multiprocessing as mp
     from paper_2311_11943_amd import cqr
@@ -353,10 +353,15 @@ def run_generator_study(args):
                 t0 = time.perf_counter()
                 for t in range(nt):
                     v = synth.q_generator_draws(f, pr, 1000 + t)
-                    cfg = cqr.Config(m=16 * pr, n=16 * pr, pr=pr, pc=1, kv=f, kh=0, b=16)
-                    plan = cqr.coded_qr_plan_create(cfg, v, None)
-                    gv, _ = cqr.coded_qr_plan_generators(plan, cfg)
-                    cqr.coded_qr_plan_destroy(plan)
+                    # the construction's definition; the library's plans hold at most 32 blocks per code
+                    # line, so where one can be made its generator must agree with this one
+                    gv = np.hstack([-0.5 * v @ v.T, v])
+                    if pr + f <= 32:
+                        cfg = cqr.Config(m=16 * pr, n=16 * pr, pr=pr, pc=1, kv=f, kh=0, b=16)
+                        plan = cqr.coded_qr_plan_create(cfg, v, None)
+                        glib, _ = cqr.coded_qr_plan_generators(plan, cfg)
+                        cqr.coded_qr_plan_destroy(plan)
+                        assert np.abs(glib - gv).max() <= 1e-14 * np.abs(gv).max()
                     rng = np.random.default_rng(5000 + t)
                     gr = gv.copy()
                     gr[:, :f] = rng.uniform(0.0, 1.0, (f, f))

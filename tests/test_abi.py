@@ -134,6 +134,25 @@ def test_solve_workspace_size():
         cqr.coded_qr_plan_destroy(p)
 
 
+def test_new_entry_points_reject_null_arguments_before_any_launch():
+    """The solve and adjoint entry points validate their arguments on the host
+    and return CQR_EINVAL without touching the device."""
+    import ctypes as C
+    cfg = cqr.Config(m=256, n=256, pr=4, pc=4, kv=1, kh=1, b=16)
+    p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(1, 4, 1), synth.r_generator_draws(4, 1, 1))
+    P = C.c_void_p(p)
+    try:
+        assert cqr.LIB.coded_qr_solve(P, None, 256, None, 256, None, 256, 1, None, 256, None, 0, None) == cqr.CQR_EINVAL
+        assert cqr.LIB.coded_qr_backward(P, None, 320, None, 256, None, 320, None, 256, None, 256, None, 0,
+                                         None) == cqr.CQR_EINVAL
+        assert cqr.LIB.coded_qr_solve_backward(P, None, 256, None, 256, None, 256, None, 256, None, 256, 1, None, 320,
+                                               None, 256, None, 256, None, 0, None) == cqr.CQR_EINVAL
+        assert cqr.coded_qr_backward_workspace_bytes(p) > cqr.coded_qr_workspace_bytes(p)
+        assert cqr.coded_qr_solve_backward_workspace_bytes(p, 0) == 0
+    finally:
+        cqr.coded_qr_plan_destroy(p)
+
+
 def test_oracle_not_imported_by_product_package():
     pkg = os.path.join(ROOT, "paper_2311_11943_amd")
     for dirpath, _, files in os.walk(pkg):
