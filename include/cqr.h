@@ -74,10 +74,15 @@ typedef struct {
   int32_t precision;   /* cqr_precision */
   int32_t lookahead;   /* 1: the panel chain runs on a plan-owned stream while a
                           second plan-owned stream applies each panel's update to
-                          the columns right of the next panel (same operations;
-                          split products may sum in another order); both fork
-                          from and join back to the caller's stream within each
-                          call.  0: everything on the caller's stream */
+                          the columns right of the next panel; both fork from and
+                          join back to the caller's stream within each call.  The
+                          update starts from the panel after its first Cholesky
+                          pass, its coefficients taken as R2^{-T} (P1^T Q_t), equal
+                          to P^T Q_t up to rounding (split products may also sum in
+                          another order).  Two plans with lookahead alive at once
+                          hold four streams, as many as a device has hardware
+                          queues by default, so their streams may share queues and
+                          lose the overlap.  0: everything on the caller's stream */
 } cqr_config;
 
 typedef struct cqr_plan_s* cqr_plan;

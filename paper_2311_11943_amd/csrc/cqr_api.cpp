@@ -33,11 +33,13 @@ struct cqr_plan_s {
   std::vector<double> gv;   // K_v x p_r row-major:  [G~_1  V~]
   std::vector<double> gh;   // p_c x K_h row-major
   int64_t npart = 0, nS = 0;
-  size_t off_part = 0, off_part2 = 0, off_S = 0, off_G = 0, off_T = 0, off_R1 = 0, ws_bytes = 0;
-  // lookahead: the panel chain's stream, the update stream and three events,
+  int64_t ldx = 0, xstride = 0;   // first-pass panel copies for the early update (0: none)
+  size_t off_part = 0, off_part2 = 0, off_S = 0, off_G = 0, off_T = 0, off_R1 = 0, off_X = 0, off_T2 = 0,
+         ws_bytes = 0;
+  // lookahead: the panel chain's stream, the update stream and four events,
   // created on first use on the device current at that time
   hipStream_t chain = nullptr, side = nullptr;
-  hipEvent_t ev_main = nullptr, ev_side = nullptr, ev_chain = nullptr;
+  hipEvent_t ev_main = nullptr, ev_side = nullptr, ev_chain = nullptr, ev_apply = nullptr;
   int side_dev = -1;
   // opt-in per-launch timing
   struct Rec { int phase; hipEvent_t a, b; double flops, bytes; };
@@ -212,6 +214,10 @@ cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws, bool second = false) {
   s.G = reinterpret_cast<double*>(b + p.off_G);
   s.T = reinterpret_cast<double*>(b + p.off_T);
   s.R1 = reinterpret_cast<double*>(b + p.off_R1);
+  s.X = p.xstride ? reinterpret_cast<double*>(b + p.off_X) : nullptr;
+  s.ldx = p.ldx;
+  s.xstride = p.xstride;
+  s.T2 = reinterpret_cast<double*>(b + p.off_T2);
   return s;
 }
 
@@ -261,15 +267,21 @@ void side_release(cqr_plan_s& p) {
   if (p.ev_main) (void)hipEventDestroy(p.ev_main);
   if (p.ev_side) (void)hipEventDestroy(p.ev_side);
   if (p.ev_chain) (void)hipEventDestroy(p.ev_chain);
+  if (p.ev_apply) (void)hipEventDestroy(p.ev_apply);
   if (p.side) (void)hipStreamDestroy(p.side);
   if (p.chain) (void)hipStreamDestroy(p.chain);
   p.side = p.chain = nullptr;
-  p.ev_main = p.ev_side = p.ev_chain = nullptr;
+  p.ev_main = p.ev_side = p.ev_chain = p.ev_apply = nullptr;
   p.side_dev = -1;
 }
 
 // The lookahead streams (default priority, no implicit synchronization with
-// the null stream) and their events on the current device.
+// the null stream) and their events on the current device.  The per-panel fork
+// and join events order work between two streams of one device only, so they
+// skip the system-scope fence (a writeback for host visibility that would
+// stall each stream at every panel); the event the caller's stream waits on
+// keeps it.
+constexpr unsigned kStreamEvent = hipEventDisableTiming | hipEventDisableSystemFence;
 bool side_ready(cqr_plan_s& p) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return false;
@@ -277,8 +289,9 @@ bool side_ready(cqr_plan_s& p) {
   side_release(p);
   const bool ok = hipStreamCreateWithFlags(&p.chain, hipStreamNonBlocking) == hipSuccess &&
                   hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
-                  hipEventCreateWithFlags(&p.ev_main, hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&p.ev_side, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&p.ev_main, kStreamEvent) == hipSuccess &&
+                  hipEventCreateWithFlags(&p.ev_side, kStreamEvent) == hipSuccess &&
+                  hipEventCreateWithFlags(&p.ev_apply, kStreamEvent) == hipSuccess &&
                   hipEventCreateWithFlags(&p.ev_chain, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     side_release(p);
@@ -350,18 +363,51 @@ void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64
 }
 
 void chol(cqr_plan_s& p, const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-          int64_t ldx, double* Rbar, int panel, const cqr::Scratch& s, hipStream_t st) {
-  prof(p, PH_CHOL, 2.0 * w * w * w * (X ? 2.0 : 1.0), 8.0 * w * w * (pass == 1 ? 3.0 : (X ? 6.0 : 4.0)), st,
-       [&] { cqr::launch_chol(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s, st); });
+          int64_t ldx, double* Rbar, int panel, const cqr::Scratch& s, hipStream_t st, double* Tcopy = nullptr) {
+  prof(p, PH_CHOL, 2.0 * w * w * w * (X ? 2.0 : 1.0),
+       8.0 * w * w * (pass == 1 ? 3.0 : (X ? 6.0 : 4.0) + (Tcopy ? 1.0 : 0.0)), st,
+       [&] { cqr::launch_chol(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s, st, Tcopy); });
+}
+
+// The product W = X^T B of an update that starts before its panel is
+// finished (X: the panel after its first Cholesky pass, mp x w; B: the
+// trailing columns), on the update stream.  It leaves the split partials, or
+// W itself (ld w) in the partial buffer when the product does not split, for
+// tn_tmul's reduction.  Its split keeps the launch to about kEarlyBlocks
+// workgroups, below the 512 that two per CU would hold: its workgroups live
+// for the whole product, and the chain's kernels, which run beside it, need
+// free slots (measured: 448 beats 512 by 2% on the n = 4096 step).
+constexpr int kEarlyBlocks = 448;
+cqr::TnArgs tn_early(cqr_plan_s& p, const double* X, int64_t ldx, const double* B, int64_t ldb, int w, int N,
+                     const cqr::Scratch& s, hipStream_t st, bool f32) {
+  const int tiles = (N + kTile - 1) / kTile;
+  const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(kEarlyBlocks / tiles, p.mp / 256));
+  cqr::TnArgs a = cqr::tn_setup(X, ldx, B, ldb, w, N, p.mp, s.part, w, nullptr, 0, s, ns, f32);
+  a.prio = chain_phase(PH_TRAIL_TN);
+  const double fl = 2.0 * w * N * (double)p.mp, by = 8.0 * (double)p.mp * ((double)w + N);
+  const double out = a.nsplit > 1 ? partial_bytes(a.nsplit, a.ntiles) : 8.0 * (double)w * N;
+  prof(p, PH_TRAIL_TN, fl, by + out, st, [&] { cqr::launch_tn_product(a, cqr::TAG_TRAIL, st); });
+  return a;
+}
+
+// out = T^T W for the W that tn_early left (T: w x w, the second pass's
+// R^{-1}): the update's coefficients against the finished panel.
+void tn_tmul(cqr_plan_s& p, const cqr::TnArgs& a, const double* T, int w, double* out, int64_t ldo,
+             hipStream_t st) {
+  const double in = a.nsplit > 1 ? partial_bytes(a.nsplit, a.ntiles) : 8.0 * (double)w * a.N;
+  prof(p, PH_REDUCE, (a.nsplit - 1.0) * w * a.N + 2.0 * w * w * (double)a.N, in + 8.0 * (w * w + (double)w * a.N),
+       st, [&] { cqr::launch_tn_reduce_tmul(a, T, w, out, ldo, st); });
 }
 
 // The split re-projection update C -= A B with the panel's first Cholesky
 // pass (c) run by one extra block of the same launch, then the split
-// reduction fused with the pass's transform C <- C T.  Returns false,
-// launching nothing, when the update would not split over K; the caller then
-// runs the update, the Cholesky and the transform separately.
+// reduction fused with the pass's transform C <- C T (the result also stored
+// to X when X != nullptr).  Returns false, launching nothing, when the update
+// would not split over K; the caller then runs the update, the Cholesky and
+// the transform separately.
 bool nn_chol(cqr_plan_s& p, double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb,
-             int64_t M, int N, int K, const cqr::CholArgs& c, const cqr::Scratch& s, hipStream_t st) {
+             int64_t M, int N, int K, const cqr::CholArgs& c, const cqr::Scratch& s, hipStream_t st,
+             double* X = nullptr, int64_t ldx = 0) {
   if (M <= 0 || N <= 0 || K <= cqr::kLeaf || c.w > cqr::kLeaf) return false;
   cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, false);
   a.prio = 1;
@@ -372,8 +418,9 @@ bool nn_chol(cqr_plan_s& p, double* C, int64_t ldc, const double* A, int64_t lda
   prof(p, PH_REPROJ_NN, fl, by + partial_bytes(a.nsplit, a.ntiles), st,
        [&] { launched = cqr::launch_nn_chol(a, c, st); });
   if (!launched) return false;
-  prof(p, PH_REDUCE, (double)a.nsplit * M * N + 2.0 * M * N * N, partial_bytes(a.nsplit, a.ntiles) + 16.0 * (double)M * N,
-       st, [&] { cqr::launch_nn_reduce_apply(a, c.T, c.w, st); });
+  prof(p, PH_REDUCE, (double)a.nsplit * M * N + 2.0 * M * N * N,
+       partial_bytes(a.nsplit, a.ntiles) + (X ? 24.0 : 16.0) * (double)M * N, st,
+       [&] { cqr::launch_nn_reduce_apply(a, c.T, c.w, X, ldx, st); });
   return true;
 }
 
@@ -512,6 +559,14 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   p->off_G = off;    off = align256(off + sizeof(double) * 2 * kLeaf * kLeaf);
   p->off_T = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
   p->off_R1 = off;   off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  p->off_T2 = off;   off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  if (b <= kLeaf) {
+    // two copies of a first-pass panel (even leading dimension, 256-byte
+    // aligned each) for the update that starts before the second pass
+    p->ldx = (p->mp + 1) / 2 * 2;
+    p->xstride = (int64_t)(align256(sizeof(double) * (size_t)(p->ldx * b)) / sizeof(double));
+    p->off_X = off;  off = align256(off + sizeof(double) * 2 * (size_t)p->xstride);
+  }
   p->ws_bytes = off;
 
   *out = p;
@@ -645,12 +700,22 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
        f32);
     nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss, f32);
   };
-  bool side_pending = false;
-  // the caller's stream waits for the side stream's update of panel k-1
+  bool side_pending = false;   // ev_side marks side-stream work the chain has not waited for
+  bool side_tail = false;      // side-stream work queued after the last ev_side record
+  // the chain waits for the side stream's update of the next panel's columns
   auto join_side = [&]() -> hipError_t {
     if (!side_pending) return hipSuccess;
     side_pending = false;
     return hipStreamWaitEvent(st, p->ev_side, 0);
+  };
+  // the chain waits for everything queued on the side stream
+  auto join_side_all = [&]() -> hipError_t {
+    if (side_tail) {
+      if (hipError_t e = hipEventRecord(p->ev_side, p->side); e != hipSuccess) return e;
+      side_pending = true;
+      side_tail = false;
+    }
+    return join_side();
   };
   // panel k's update of columns [c1 + b, N) on the side stream
   auto fork_side = [&](int64_t c0, int64_t from) -> hipError_t {
@@ -659,7 +724,10 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     if (e != hipSuccess) return e;
     trail(c0, from, N, s2, p->side);
     e = hipEventRecord(p->ev_side, p->side);
-    if (e == hipSuccess) side_pending = true;
+    if (e == hipSuccess) {
+      side_pending = true;
+      side_tail = false;
+    }
     return e;
   };
   for (int k = pb; k < pe; ++k) {
@@ -681,6 +749,15 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       const double* W1 = s.G;
       int64_t ldw1 = b;
       bool chol1 = false;   // first Cholesky pass already launched
+      // Early update (with the first pass inside the re-projection's
+      // launches): panel k's update of the columns [c1 + b, N) starts on the
+      // side stream from the first-pass panel P1, which the first pass's
+      // transform also stores to X, while the chain runs the second pass.  Its
+      // reduction folds in the second pass's R2^{-1} (R_t = R2^{-T} P1^T Q_t =
+      // P^T Q_t), and the update Q_t -= P R_t waits for the finished panel P.
+      // X alternates between two buffers: the chain writes panel k+1's copy
+      // before it waits for panel k's update.
+      double* X = (next && c1 + b < N && s.X) ? s.X + (k & 1) * s.xstride : nullptr;
       if (p->cfg.reproject && k > 0) {
         // S = Q[:, :c0]^T P (rows < c0, also added into R[:c0, panel]);  P -= Q[:, :c0] S.
         // The first Cholesky pass needs only the Gram rows and the update only
@@ -690,7 +767,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
         W1 = s.S + c0;
         ldw1 = c1;
         chol1 = nn_chol(*p, P, ldq, Q, ldq, s.S, c1, mp, (int)b, (int)c0,
-                        cqr::chol_args(W1, ldw1, (int)b, 1, nullptr, 0, nullptr, 0, nullptr, k, s), s, st);
+                        cqr::chol_args(W1, ldw1, (int)b, 1, nullptr, 0, nullptr, 0, nullptr, k, s), s, st, X, s.ldx);
         if (!chol1) nn(*p, PH_REPROJ_NN, P, ldq, Q, ldq, s.S, c1, mp, (int)b, (int)c0, s, st);
       } else {
         tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, (int)b, mp, s.G, b, nullptr, 0, s, st);
@@ -699,26 +776,60 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
         chol(*p, W1, ldw1, (int)b, 1, nullptr, 0, nullptr, 0, nullptr, k, s, st);
         apply(*p, P, ldq, (int)b, s, st);
       }
+      const bool early = chol1 && X;
+      // (recorded before the chain's wait below, so the side stream's product
+      // does not wait for the chain to pass it)
+      if (early)
+        if (hipError_t e = hipEventRecord(p->ev_main, st); e != hipSuccess) return hip_fail(e);
       // Second pass.  With lookahead the same product also gives
       // X = P1^T Q_next, and the Cholesky kernel forms the next panel's
       // coefficients R[panel, next] = (P1 R2^{-1})^T Q_next = R2^{-T} X.
-      // Q_next must first carry panel k-1's update from the side stream.
+      // Q_next must first carry panel k-1's update from the side stream.  (The
+      // wait is queued before panel k's early update records its own event.)
       if (hipError_t e = join_side(); e != hipSuccess) return hip_fail(e);
+      cqr::TnArgs ea{};
+      if (early) {
+        if (hipError_t e = hipStreamWaitEvent(p->side, p->ev_main, 0); e != hipSuccess) return hip_fail(e);
+        ea = tn_early(*p, X, s.ldx, Q + (c1 + b) * ldq, ldq, (int)b, (int)(N - c1 - b), s2, p->side, f32);
+      }
       tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, next ? 2 * (int)b : (int)b, mp, s.G, b, nullptr, 0, s, st);
       chol(*p, s.G, b, (int)b, 2, R + c0 + c0 * ldr, ldr, next ? s.G + b * b : nullptr, b,
-           next ? R + c0 + c1 * ldr : nullptr, k, s, st);
+           next ? R + c0 + c1 * ldr : nullptr, k, s, st, early ? s.T2 : nullptr);
       // P <- P1 R2^{-1}, and with lookahead Q_next -= P R[panel, next] (one
       // launch in FP64; the FP32 form keeps its FP32 update)
       const bool fused = next && !f32 &&
                          apply_update(*p, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, (int)b, s, st);
       if (!fused) apply(*p, P, ldq, (int)b, s, st);
       if (next) {
-        // the remaining columns on the side stream
         if (!fused)
           nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st, f32);
-        if (c1 + b < N)
+        if (early) {
+          // the early update's reduction and rank-b update, after the panel
+          hipError_t e = hipEventRecord(p->ev_apply, st);
+          if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_apply, 0);
+          if (e != hipSuccess) return hip_fail(e);
+          // The next panel's chain needs only panel k+2's columns from this
+          // update: they are updated first and marked by ev_side, and the
+          // columns after them are updated while the chain moves on (the
+          // chain touches them only after join_side_all).
+          double* Rb = R + c0 + (c1 + b) * ldr;
+          tn_tmul(*p, ea, s.T2, (int)b, Rb, ldr, p->side);
+          const int64_t near = std::min<int64_t>(b, N - c1 - b);
+          nn(*p, PH_TRAIL_NN, Q + (c1 + b) * ldq, ldq, P, ldq, Rb, ldr, mp, (int)near, (int)b, s2, p->side, f32);
+          e = hipEventRecord(p->ev_side, p->side);
+          if (e != hipSuccess) return hip_fail(e);
+          side_pending = true;
+          if (c1 + b + near < N) {
+            nn(*p, PH_TRAIL_NN, Q + (c1 + b + near) * ldq, ldq, P, ldq, Rb + near * ldr, ldr, mp,
+               (int)(N - c1 - b - near), (int)b, s2, p->side, f32);
+            side_tail = true;
+          }
+        } else if (c1 + b < N) {
+          // the remaining columns on the side stream
           if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
+        }
       } else if (c1 < N) {
+        if (hipError_t e = join_side_all(); e != hipSuccess) return hip_fail(e);
         trail(c0, c1, N, s, st);
       }
       continue;
@@ -731,7 +842,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     }
     factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
     if (c1 >= N) continue;
-    if (hipError_t e = join_side(); e != hipSuccess) return hip_fail(e);
+    if (hipError_t e = join_side_all(); e != hipSuccess) return hip_fail(e);
     if (next && c1 + b < N) {
       trail(c0, c1, c1 + b, s, st);
       if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
@@ -739,7 +850,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       trail(c0, c1, N, s, st);
     }
   }
-  if (hipError_t e = join_side(); e != hipSuccess) return hip_fail(e);
+  if (hipError_t e = join_side_all(); e != hipSuccess) return hip_fail(e);
   if (la) {
     // the caller's stream waits for the chain (which has joined the updates)
     hipError_t e = hipEventRecord(p->ev_chain, st);

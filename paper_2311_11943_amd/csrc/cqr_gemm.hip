@@ -545,11 +545,11 @@ __device__ __forceinline__ void chol_blocked(int tid, double (*Rl)[kLeaf + 1], d
 // C = op(A) B for 64 x 64 LDS matrices (row-major, padded): op(A) = A, or
 // A^T when TRANS_A.  UPPER: A and B upper triangular (C[i][j] needs only
 // k in [i, j]; k blocks left of the row block are skipped).  Wave v computes
-// rows 16v..16v+15 and stores C[i][j] (i, j < w) into the column-major global
-// matrix out (ld ldo).
+// rows 16v..16v+15 and stores C[i][j] (i < w, j < wc) into the column-major
+// global matrix out (ld ldo).
 template <bool TRANS_A, bool UPPER>
 __device__ __forceinline__ void lds_mm_store(int tid, const double (*Al)[kLeaf + 1], const double (*Bl)[kLeaf + 1],
-                                             int w, double* out, int64_t ldo) {
+                                             int w, int wc, double* out, int64_t ldo) {
   const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
   v4d acc[4];
 #pragma unroll
@@ -569,8 +569,80 @@ __device__ __forceinline__ void lds_mm_store(int tid, const double (*Al)[kLeaf +
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = 16 * y + 4 * r + g;
-      if (i < w && j < w) out[i + (int64_t)j * ldo] = acc[y][r];
+      if (i < w && j < wc) out[i + (int64_t)j * ldo] = acc[y][r];
     }
+}
+
+// The split reduction of a trailing-update product W = P1^T Q_t formed from
+// a panel after its first Cholesky pass, with the second pass's transform
+// folded in: out = T^T W (T = R2^{-1}, w x w upper triangular) equals
+// (P1 T)^T Q_t, the coefficients against the finished panel P = P1 T.  M = w
+// <= 64, so the product has a single tile row; four blocks share a 64-column
+// tile, block cg taking the 16 columns that two wave quadrants of the product
+// hold in their accumulator registers (quadrant column half cg >> 1, lane
+// column group cg & 1).  The 64 x 16 strip of W is summed in split order into
+// LDS (or read from a.C, where a product without a split stored it) and
+// multiplied by T^T on MFMA, wave v forming rows 16v .. 16v + 15.
+__global__ __launch_bounds__(256) void tn_reduce_tmul_kernel(TnArgs a, const double* T, int w, double* out,
+                                                             int64_t ldo) {
+  __shared__ double Wl[kLeaf][16 + 1];
+  __shared__ double Tl[kLeaf][kLeaf + 1];
+  const int tile = blockIdx.x >> 2, cg = blockIdx.x & 3, tid = threadIdx.x;
+  const int lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int64_t jc = (int64_t)tile * kTile + (cg >> 1) * 32 + 16 * (cg & 1);   // first column of the strip
+  const int wc = (int)std::max<int64_t>(0, std::min<int64_t>(16, a.N - jc));
+  double tv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, k = e & 63, i = e >> 6;
+    tv[q] = (k < w && i < w) ? T[k + (int64_t)i * w] : 0.0;
+  }
+  if (a.nsplit > 1) {
+    // thread (row half wr, row group qh, lane) sums 4 values of quadrant
+    // wr + 2 (cg >> 1), lane group 2 qh + (cg & 1)
+    const int wr = tid >> 7, qh = (tid >> 6) & 1;
+    double v[4];
+    sum_partials4(a.part, a.nsplit, a.ntiles, tile, wr | ((cg >> 1) << 1), (qh << 1) | (cg & 1), lane, v);
+    const int i = wr * 32 + 16 * qh + li;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = colsub(u, g, a.f32);
+      Wl[i][j] = (i < w && j < wc) ? v[u] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q, i = e & 63, j = e >> 6;
+      Wl[i][j] = (i < w && j < wc) ? a.C[i + (jc + j) * a.ldc] : 0.0;
+    }
+  }
+  // Tl[k][i] = T[k][i]: the transposed operand of the product
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    Tl[e & 63][e >> 6] = tv[q];
+  }
+  __syncthreads();
+  const int wave = tid >> 6;
+  v4d acc = v4d{0, 0, 0, 0};
+#pragma unroll
+  for (int k0 = 0; k0 < kLeaf; k0 += 16)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      acc = mfma(Wl[k][li], Tl[k][16 * wave + li], acc);
+    }
+  const int i = 16 * wave + li;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = 4 * r + g;
+    if (i < w && j < wc) out[i + (jc + j) * ldo] = acc[r];
+  }
+}
+
+void launch_tn_reduce_tmul(const TnArgs& a, const double* T, int w, double* out, int64_t ldo, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0) return;
+  hipLaunchKernelGGL(tn_reduce_tmul_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w, out, ldo);
 }
 
 // C = T^T X with T (64 x 64, upper triangular, row-major LDS) and X (w x w,
@@ -676,6 +748,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
     if (tx < w && k < w) {
       a.T[tx + k * w] = Tl[tx][k];
       if (pass == 1) a.R1[tx + k * w] = Rl[tx][k];
+      if (pass == 2 && a.Tcopy) a.Tcopy[tx + k * w] = Tl[tx][k];
     }
   }
   if (pass == 2) {
@@ -696,7 +769,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
       Tl[tx][k] = r1v[q];
     }
     __syncthreads();
-    lds_mm_store<false, true>(tid, Rl, Tl, w, a.Rout, a.ldr);
+    lds_mm_store<false, true>(tid, Rl, Tl, w, w, a.Rout, a.ldr);
   }
   if (tid == 0 && s_bad && *a.info == 0) *a.info = 1 + a.panel;
 }
@@ -717,12 +790,14 @@ CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, 
   c.w = w; c.pass = pass; c.panel = panel;
   c.T = s.T; c.R1 = s.R1; c.Rout = Rout; c.ldr = ldr; c.info = s.info;
   c.X = X; c.ldx = ldx; c.Rbar = Rbar;
+  c.Tcopy = nullptr;
   return c;
 }
 
 void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st) {
-  const CholArgs c = chol_args(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s);
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st, double* Tcopy) {
+  CholArgs c = chol_args(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s);
+  c.Tcopy = Tcopy;
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, c);
 }
 
@@ -901,44 +976,49 @@ __device__ __forceinline__ void nn_mma(Acc (&acc)[4], const double (*sBb)[64 + 1
 }
 
 // C -= A B for K <= 64 (the trailing update: K = b): every load of the tile
-// (C, A, the B slab) is issued before the first product.
+// (C, A, the B slab) is issued before the first product.  The tile loop is
+// grid-strided (the launch has one block per tile).
 template <int TAG, bool F32>
 __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
   if (a.prio) __builtin_amdgcn_s_setprio(2);
   typedef typename AccT<F32>::type Acc;
   __shared__ double sB[NK][64 + 1];
-  int tm, tn;
-  xcd_tile(blockIdx.x, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
-  const NnTile t = nn_tile_at(a, tm, tn);
-  double cval[16];
+  for (int blk = blockIdx.x; blk < a.ntiles; blk += gridDim.x) {
+    int tm, tn;
+    xcd_tile(blk, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
+    const NnTile t = nn_tile_at(a, tm, tn);
+    double cval[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
-    cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
-  }
-  double xa[16];
-  if (a.K == NK && a.vec) {
-    v2d rb[8];
-    nn_load_a(a, t, 0, xa);
-    nn_load_b(t, 0, rb);
-    __builtin_amdgcn_sched_barrier(0);
-    nn_put_b(sB, t, rb);
-  } else {
-    nn_load_tail(a, t, 0, a.K, xa, sB);
-  }
-  __syncthreads();
-  Acc acc[4];
-#pragma unroll
-  for (int y = 0; y < 4; ++y) acc[y] = Acc{0, 0, 0, 0};
-  nn_mma(acc, sB, t, xa);
-  if (!t.aok) return;
-#pragma unroll
-  for (int y = 0; y < 4; ++y)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = t.jb + 16 * y + colsub(r, t.g, F32);
-      if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
+    for (int e = 0; e < 16; ++e) {
+      const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
+      cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
     }
+    double xa[16];
+    if (blk != (int)blockIdx.x) __syncthreads();   // the previous tile's reads of sB are done
+    if (a.K == NK && a.vec) {
+      v2d rb[8];
+      nn_load_a(a, t, 0, xa);
+      nn_load_b(t, 0, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      nn_put_b(sB, t, rb);
+    } else {
+      nn_load_tail(a, t, 0, a.K, xa, sB);
+    }
+    __syncthreads();
+    Acc acc[4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[y] = Acc{0, 0, 0, 0};
+    nn_mma(acc, sB, t, xa);
+    if (t.aok) {
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = t.jb + 16 * y + colsub(r, t.g, F32);
+          if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
+        }
+    }
+  }
 }
 
 // The second pass's panel transform and the lookahead update in one launch:
@@ -1152,7 +1232,8 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
 // 64 strip of C - sum(partials) is staged in LDS and multiplied by T on MFMA
 // (wave q forms output columns 16q .. 16q + 15) before it is stored, so the
 // transform needs no launch or pass over P of its own.
-__global__ __launch_bounds__(256) void nn_reduce_apply_kernel(NnArgs a, const double* T, int w) {
+__global__ __launch_bounds__(256) void nn_reduce_apply_kernel(NnArgs a, const double* T, int w, double* X,
+                                                              int64_t ldx) {
   __builtin_amdgcn_s_setprio(2);   // panel chain
   __shared__ double sP[16][64 + 1];
   __shared__ double sT[64][64 + 1];
@@ -1197,13 +1278,16 @@ __global__ __launch_bounds__(256) void nn_reduce_apply_kernel(NnArgs a, const do
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int j = 16 * qg + 4 * r + g;
-    if (j < w) a.C[i + (int64_t)j * a.ldc] = acc[r];
+    if (j < w) {
+      a.C[i + (int64_t)j * a.ldc] = acc[r];
+      if (X) X[i + (int64_t)j * ldx] = acc[r];
+    }
   }
 }
 
-bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, hipStream_t st) {
+bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, double* X, int64_t ldx, hipStream_t st) {
   if (a.M <= 0 || a.nsplit <= 1 || a.tilesN != 1 || a.N != w || w > kLeaf || a.f32) return false;
-  hipLaunchKernelGGL(nn_reduce_apply_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w);
+  hipLaunchKernelGGL(nn_reduce_apply_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w, X, ldx);
   return true;
 }
 

@@ -70,6 +70,9 @@ struct Scratch {
   double* G;          // second-pass Gram and lookahead product (kLeaf x 2 kLeaf)
   double* T;          // inverse Cholesky factor (kLeaf x kLeaf)
   double* R1;         // first-pass Cholesky factor (kLeaf x kLeaf)
+  double* X;          // two first-pass panel copies (ldx x b each, xstride doubles apart)
+  int64_t ldx, xstride;
+  double* T2;         // the second pass's inverse factor, kept for the update stream
 };
 
 // Kernel-instance tags: each use of a product kernel gets its own symbol, so
@@ -102,6 +105,10 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
 void launch_tn_product(const TnArgs& a, int tag, hipStream_t st);
 // Sum the partials into C (and C2) in split order (nsplit > 1 only).
 void launch_tn_reduce(const TnArgs& a, hipStream_t st);
+// out (w x N, ldo) = T^T W for the product W = A^T B of a (a.M = w <= 64 rows,
+// one tile row): W is summed from the split partials (nsplit > 1) or read from
+// a.C (nsplit == 1, where the product stored it); T is w x w (ld w).
+void launch_tn_reduce_tmul(const TnArgs& a, const double* T, int w, double* out, int64_t ldo, hipStream_t st);
 
 // C (M x N) -= A (M x K) B (K x N).
 struct NnArgs {
@@ -128,6 +135,7 @@ struct CholArgs {
   double* T; double* R1; double* Rout; int64_t ldr; int* info;
   const double* X; int64_t ldx;     // pass 2, optional: w x w product P1^T Q_next
   double* Rbar;                     // T^T X (ld ldr)
+  double* Tcopy;                    // pass 2, optional: second destination of T (w x w, ld w)
 };
 
 CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
@@ -136,18 +144,20 @@ CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, 
 // Upper Cholesky factor of the panel Gram matrix W (w x w, ld ldw, w <= kLeaf).
 // pass 1: R1 <- chol(W), T <- R1^{-1}.  pass 2: R2 <- chol(W), T <- R2^{-1},
 // Rout (ldr) <- R2 R1, and, if X != nullptr, Rbar (ldr) <- T^T X (X: w x w,
-// ld ldx).  Breakdown sets info[0] = 1 + panel.
+// ld ldx).  On the second pass T is also stored to Tcopy when it is not
+// nullptr.  Breakdown sets info[0] = 1 + panel.
 void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st);
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st, double* Tcopy = nullptr);
 
 // The split re-projection update (launch_nn_product with nsplit > 1) with the
 // first Cholesky pass described by c run by one extra block of the same
 // launch; returns false, launching nothing, when the update does not split.
 bool launch_nn_chol(const NnArgs& a, const CholArgs& c, hipStream_t st);
 // The split reduction of a panel update (a.N = w <= 64 columns, one column
-// tile) fused with the panel transform C <- C T (T: w x w, ld w); false,
-// launching nothing, for any other shape.
-bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, hipStream_t st);
+// tile) fused with the panel transform C <- C T (T: w x w, ld w); the result
+// is also stored to X (ld ldx) when X != nullptr.  False, launching nothing,
+// for any other shape.
+bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, double* X, int64_t ldx, hipStream_t st);
 // The panel transform A <- A T (A: M x w, the update's left operand; T: w x w,
 // ld w) and the rank-w update C -= A B in one launch (K = w <= 64, one column
 // tile, FP64); false, launching nothing, for any other shape.
