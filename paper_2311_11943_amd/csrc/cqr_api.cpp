@@ -244,8 +244,11 @@ hipEvent_t take_event(cqr_plan_s& p) {
     p.pool.pop_back();
     return e;
   }
+  // timing events with a device-scope release: a system-scope one (the
+  // default) stalls the stream at every record and changes the schedule
+  // being measured
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess) return nullptr;
   return e;
 }
 
