@@ -159,10 +159,14 @@ def test_failures_without_horizontal_code(cqr, storage):
     assert np.abs(Qg - out["Q"]).max() < 1e-11
 
 
-@pytest.mark.parametrize("sid,n,pr,K,b", [("innode", 512, 8, 2, 64), ("ragged", 240, 4, 1, 16)])
+@pytest.mark.parametrize("sid,n,pr,K,b", [("innode", 512, 8, 2, 64), ("ragged", 240, 4, 1, 16),
+                                          ("b32_5x5", 480, 5, 1, 32)])
 def test_lookahead_matches_single_stream(cqr, sid, n, pr, K, b):
-    """The second-stream schedule runs the same operations; only split-product
-    summation order may differ.  Both agree with the oracle."""
+    """The second-stream schedule computes each panel's update coefficients as
+    R2^{-T} (P1^T Q_t) from the first-pass panel instead of P^T Q_t, and splits
+    products differently: equal up to rounding.  Both agree with the oracle.
+    (b = 32 on a 5 x 5 grid: the early update's column counts end in half
+    tiles, and its near launch is narrower than a tile.)"""
     print(f"[case] lookahead {sid}", flush=True)
     A, v, gh, lay = make_inputs(n, pr, K, b, "in" if sid == "innode" else "out", seed=7)
     sched = synth.draw_schedule("random", n // b, pr, pr, 7, nfail=1)
