@@ -222,6 +222,45 @@ def run_sweep(args):
             torch.cuda.empty_cache()
 
 
+def run_peaks(args):
+    """Practical ceilings of this device beside the published peaks used for
+    the rooflines: a large square GEMM in FP64 and FP32 through torch (the
+    vendor BLAS, MFMA) and a device-to-device copy (HBM read + write)."""
+    import torch
+    dev = torch.device("cuda:0")
+
+    def best_ms(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            z.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(z))
+        return min(ts)
+
+    out = {"peaks": "measured ceilings vs published", "device": torch.cuda.get_device_name(0)}
+    n = 8192
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        x = torch.randn(n, n, device=dev, dtype=dt)
+        y = torch.randn(n, n, device=dev, dtype=dt)
+        zz = torch.empty(n, n, device=dev, dtype=dt)
+        ms = best_ms(lambda: torch.matmul(x, y, out=zz))
+        out[f"gemm_{name}_tflops"] = round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2)
+        del x, y, zz
+    out["published_fp64_mfma_tflops"] = PEAK["fp64_mfma_tflops"]
+    out["published_fp32_mfma_tflops"] = PEAK["fp32_mfma_tflops"]
+    src = torch.ones(256 << 20, device=dev, dtype=torch.float64)   # 2 GiB
+    dst = torch.empty_like(src)
+    ms = best_ms(lambda: dst.copy_(src))
+    out["copy_gbs"] = round(2.0 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
+    out["published_hbm_gbs"] = PEAK["hbm_gbs"]
+    print(json.dumps(out), flush=True)
+
+
 def run_adjoint(args):
     """Tall-skinny least squares through the coded QR and its adjoint:
     m = 65536, n = 512 Gaussian A and b, 16 x 1 grid (4096-row blocks), b = 64,
@@ -413,6 +452,9 @@ def main():
                          "the structured and of a random Q-side generator (f = 2..6, p_r = 16, 32, 64)")
     ap.add_argument("--study-scale", type=float, default=1.0, help="scales the study's trial counts")
     ap.add_argument("--study-procs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the device's practical ceilings beside the published peaks: FP64 and FP32 "
+                         "GEMM through torch (the vendor BLAS) and a device copy; one JSON line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -428,6 +470,9 @@ def main():
         return
     if args.adjoint:
         run_adjoint(args)
+        return
+    if args.peaks:
+        run_peaks(args)
         return
 
     import torch
