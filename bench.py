@@ -452,6 +452,8 @@ def main():
                          "the structured and of a random Q-side generator (f = 2..6, p_r = 16, 32, 64)")
     ap.add_argument("--study-scale", type=float, default=1.0, help="scales the study's trial counts")
     ap.add_argument("--study-procs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="limit the oracle's BLAS threads in the cpu_baseline leg (0: all host threads)")
     ap.add_argument("--peaks", action="store_true",
                     help="measure the device's practical ceilings beside the published peaks: FP64 and FP32 "
                          "GEMM through torch (the vendor BLAS) and a device copy; one JSON line")
@@ -688,15 +690,22 @@ def main():
         if n > 8192:
             out["cpu_baseline"] = None
         else:
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                oc.run(prob)
-            tc = (time.perf_counter() - t0) / reps
+            import contextlib
+            limit = contextlib.nullcontext()
+            if args.cpu_threads > 0:
+                from threadpoolctl import threadpool_limits
+                limit = threadpool_limits(limits=args.cpu_threads)
+                cores = args.cpu_threads
+            with limit:
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    oc.run(prob)
+                tc = (time.perf_counter() - t0) / reps
             out["cpu_baseline"] = {"value": round(F / tc / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
                                    "kind": "oracle",
                                    "sample": f"{reps} full oracle step(s) of the same workload (encode, ICGS "
                                              f"factor with the same failures, recovery, post-orth), "
-                                             f"{tc:.2f} s each"}
+                                             f"{tc * 1e3:.1f} ms each"}
     print(json.dumps(out))
 
 
