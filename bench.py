@@ -275,7 +275,8 @@ def run_adjoint(args):
     from paper_2311_11943_amd import cqr
     dev = torch.device("cuda:0")
     m, n, pr, K, b = 65536, 512, 16, 2, 64
-    cfg = cqr.Config(m, n, pr, 1, K, 0, b, cqr.CQR_OUT_OF_NODE)
+    prec = cqr.CQR_TRAIL_FP32 if args.precision == "fp32" else cqr.CQR_FP64
+    cfg = cqr.Config(m, n, pr, 1, K, 0, b, cqr.CQR_OUT_OF_NODE, precision=prec)
     # two nodes fail at once at a random panel (R is protected by its checksum rows)
     sched = synth.draw_schedule("burst", n // b, pr, 1, args.seed, nfail=2)
     v = synth.q_generator_draws(K, pr, args.seed)
@@ -332,12 +333,13 @@ def run_adjoint(args):
     b_fl = 6.0 * mp * n * n + 2.0 * n ** 3
     print(json.dumps({
         "metric": "coded-QR least-squares forward + adjoint time", "value": round(fm + bm, 4), "unit": "ms",
-        "higher_is_better": False, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+        "higher_is_better": False, "steps": args.steps, "warmup": args.warmup,
+        "dtype": "f64" if args.precision == "fp64" else "f32 trailing update / f64 (adjoint f64)",
         "data": "synthetic",
         "config": {"workload": "c4: m=65536, n=512 Gaussian A and b, 16x1 grid (4096-row blocks), b=64, "
                                "K_v=2 out-of-node, no horizontal code (R protected by its checksum rows), "
                                "2 nodes failing at once at a random panel",
-                   "m": m, "n": n, "grid": "16x1", "b": b, "K_v": K,
+                   "m": m, "n": n, "grid": "16x1", "b": b, "K_v": K, "precision": args.precision,
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched]},
         "forward_ms": round(fm, 4), "backward_ms": round(bm, 4),
         "forward_tflops": round(f_fl / (fm * 1e-3) / 1e12, 3), "backward_tflops": round(b_fl / (bm * 1e-3) / 1e12, 3),
