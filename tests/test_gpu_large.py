@@ -1,0 +1,151 @@
+"""Full-size checks of the two large workloads, run through the C ABI in the
+launch configuration bench.py times (lookahead on, the bench's seeds and
+failure schedules), by properties that hold at any size:
+
+- every recovery restores the erased blocks of Q~ and R to the values they had
+  before the erasure (FP64: <= 1e-10 relative to the matrix's largest entry;
+  with FP32 trailing updates, the finished columns to the same bound);
+- A = Q_1 R_1 (relative Frobenius residual), orthogonality of Q~ and of the
+  post-orthogonalized G_0 Q_1, and the checksum rows of the finished factor
+  equal to G_v Q_1 (relative to Q_1's largest entry).
+
+n = 16384 (8 x 8 grid, b = 128, K = 4 out-of-node, A = U diag(s) V^T with
+cond 1e6, a reverse-diagonal storm of 4 nodes per grid row every 16 panels) in
+FP64 and with FP32 trailing updates; n = 32768 (16 x 16 grid, b = 256, K = 8
+in-node, Gaussian A, storms of 4 nodes per row) in FP64.  The oracle cannot
+run at these sizes; the n = 4096 workload is compared with it element by
+element in test_gpu_fullsize.py.
+
+The orthogonality bounds grow with n: ||I - Q^T Q||_F sums n^2 entries of
+rounding size, so the 1e-12 bound used up to n = 4096 is below the rounding
+floor here (measured 1.9e-12 at n = 16384 and 3.4e-12 at n = 32768).
+"""
+import math
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _run_checked(q, A_dev, sched):
+    """encode, factor with the schedule's erasures and recoveries, comparing
+    each recovery with a copy taken just before the erasure.  Returns (At, R,
+    worst relative error of Q~'s finished columns, of all of Q~, of R); NaN
+    (an entry left erased) fails every bound."""
+    c = q.cfg
+    At, R = q.alloc()
+    At[:c.m, :c.n].copy_(A_dev)
+    q.encode(At)
+    k, errs = 0, []
+    for t, nodes in list(sched) + [(c.npanels, None)]:
+        q.factor(At, R, k, t)
+        k = t
+        if nodes is None:
+            break
+        At0, R0 = At.clone(), R.clone()
+        q.erase(At, R, nodes)
+        q.recover(At, R, nodes)
+        done = t * c.b
+
+        def rel(x, x0):
+            return ((x - x0).abs().max() / x0.abs().max()).item()
+        e = (rel(At[:, :done], At0[:, :done]), rel(At, At0), rel(R, R0))
+        print(f"    event at panel {t}: {len(nodes)} nodes, recovery: finished columns {e[0]:.2e}, "
+              f"all of Q~ {e[1]:.2e}, R {e[2]:.2e}", flush=True)
+        errs.append(e)
+        del At0, R0
+    worst = [max((e[i] for e in errs), key=lambda x: float("inf") if math.isnan(x) else x) for i in range(3)]
+    return At, R, worst
+
+
+def _properties(q, A_dev, At, R):
+    c = q.cfg
+    m, n = c.m, c.n
+    Q1 = At[:m, :n]
+    res = (torch.linalg.norm(A_dev - Q1 @ R[:n, :n]) / torch.linalg.norm(A_dev)).item()
+    Qt = At[:, :n]
+    eye = torch.eye(n, device=At.device, dtype=torch.float64)
+    orth = torch.linalg.norm(eye - Qt.T @ Qt).item()
+    # checksum block rows of the finished factor against G_v Q_1
+    gv = torch.tensor(q.generators()[0], device=At.device, dtype=torch.float64)
+    bs = m // c.pr
+    worst = 0.0
+    for kk in range(c.kv):
+        want = sum(gv[kk, t] * Q1[t * bs:(t + 1) * bs] for t in range(c.pr))
+        got = At[m + kk * bs:m + (kk + 1) * bs, :n]
+        worst = max(worst, ((got - want).abs().max() / Q1.abs().max()).item())
+    from paper_2311_11943_amd import cqr
+    Qp = cqr.col_major(m, n, At.device)
+    q.postorth(At, Qp)
+    orth_post = torch.linalg.norm(eye - Qp.T @ Qp).item()
+    return res, orth, worst, orth_post
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_n16384_properties(precision):
+    import bench
+    from oracle import coded_qr as oc
+    from paper_2311_11943_amd import cqr
+
+    w = bench.WORKLOADS["c3"]
+    n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
+    ftol = oc.f_tolerated(K, pr, oc.OUT_OF_NODE)
+    inp = bench.workload_inputs("c3", ftol, 0)
+    print(f"[case] n = {n}, {precision}, schedule {inp['schedule']}", flush=True)
+    dev = torch.device("cuda:0")
+    A_dev = cqr.to_device_colmajor(bench.conditioned_input(n, 1e6, 0, dev), dev)
+    prec = cqr.CQR_TRAIL_FP32 if precision == "fp32" else cqr.CQR_FP64
+    q = cqr.CodedQR(cqr.Config(n, n, pr, pr, K, K, b, cqr.CQR_OUT_OF_NODE, lookahead=1, precision=prec),
+                    inp["v"], inp["gh"], dev)
+    At, R, (rec_fin, rec_q, rec_r) = _run_checked(q, A_dev, inp["schedule"])
+    torch.cuda.synchronize()
+    assert q.info() == 0
+    res, orth, chk, orth_post = _properties(q, A_dev, At, R)
+    q.close()
+    print(f"    residual {res:.2e}  orth {orth:.2e}  checksum {chk:.2e}  orth post {orth_post:.2e}", flush=True)
+    assert rec_fin <= 1e-10
+    assert chk <= 1e-12
+    if precision == "fp64":
+        assert rec_q <= 1e-10 and rec_r <= 1e-10
+        assert res <= 1e-12 and orth <= 1e-11 and orth_post <= 1e-11
+    else:
+        # unfinished columns and R carry the FP32 rounding of the updates into
+        # their checksums; the FP32 form's backward error is ~u32 sqrt(n), and
+        # its orthogonality bound is the target's 1e-5
+        assert rec_q <= 1e-5 and rec_r <= 1e-5
+        assert res <= 1e-4 and orth <= 1e-5 and orth_post <= 1e-5
+
+
+def test_n32768_properties():
+    import bench
+    from oracle import coded_qr as oc
+    from paper_2311_11943_amd import cqr
+
+    w = bench.WORKLOADS["c5"]
+    n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
+    ftol = oc.f_tolerated(K, pr, oc.IN_NODE)
+    inp = bench.workload_inputs("c5", ftol, 0)
+    print(f"[case] n = {n}, fp64, {len(inp['schedule'])} failure events", flush=True)
+    dev = torch.device("cuda:0")
+    A_dev = cqr.to_device_colmajor(inp["A"], dev)
+    del inp["A"]
+    q = cqr.CodedQR(cqr.Config(n, n, pr, pr, K, K, b, cqr.CQR_IN_NODE, lookahead=1), inp["v"], inp["gh"], dev)
+    At, R, (rec_fin, rec_q, rec_r) = _run_checked(q, A_dev, inp["schedule"])
+    torch.cuda.synchronize()
+    assert q.info() == 0
+    res, orth, chk, orth_post = _properties(q, A_dev, At, R)
+    q.close()
+    print(f"    residual {res:.2e}  orth {orth:.2e}  checksum {chk:.2e}  orth post {orth_post:.2e}", flush=True)
+    assert rec_fin <= 1e-10 and rec_q <= 1e-10 and rec_r <= 1e-10
+    # With K = 8 in-node checksums and 4 failures per block column, a decode
+    # uses 4 of the surviving checksum rows; those it does not use keep values
+    # consistent with the erased data, from which the restored blocks differ by
+    # the decode's rounding (~1e-12 absolute, ~1e-11 against Q_1's small
+    # entries), and this adds up over the 7 storms (measured 2.6e-10).  At
+    # n = 16384 every checksum row takes part in every decode (K = f = 4) and
+    # the relation holds to 1e-12.  Post-orthogonalization inherits the drift
+    # (measured 1.9e-10).
+    assert chk <= 1e-9
+    assert res <= 1e-12 and orth <= 1e-11 and orth_post <= 1e-9
