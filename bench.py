@@ -68,6 +68,10 @@ KERNEL_OF = {
 }
 
 
+# the trailing update's kernel for panels wider than 64 columns (K = b > 64)
+LONG_K_UPDATE = "nn_kernel<false, 0, false>"
+
+
 def model_flops(mp, n, d, b):
     return mp * (4.0 * n * n + 4.0 * n * d + 4.0 * n * b)
 
@@ -620,8 +624,10 @@ def main():
         # the kernel holding the most time among phases that are exactly one
         # kernel symbol (so rocprofv3's per-kernel average describes the same launches)
         def kernel_of(phase):
-            # the trailing products are the FP32 instances in the mixed form
             k = KERNEL_OF[phase]
+            if phase == "trailing_update" and b > 64:
+                k = LONG_K_UPDATE      # panels wider than 64 columns: the long-K update kernel
+            # the trailing products are the FP32 instances in the mixed form
             return k.replace("<0, false>", "<0, true>") if args.precision == "fp32" else k
 
         dom = max((k for k in SINGLE_KERNEL_PHASES if rep[k]["launches"]), key=lambda k: rep[k]["ms"])

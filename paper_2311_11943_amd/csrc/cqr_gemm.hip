@@ -1319,12 +1319,141 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
   return a;
 }
 
+// In-place rank-K update C (M x N) -= A (M x K) B (K x N) for K > 64 (the
+// trailing update of panels wider than 64 columns, long re-projections), with
+// the product kernel's pipeline: 64 x 64 output tile per block, 4 waves each
+// a 32 x 32 quadrant, both operands staged through LDS in slabs of KC
+// k-values (slab s multiplied while slab s+1 lands in one register set and
+// slab s+2 is requested into the other).  A (i contiguous) is transposed into
+// the product kernel's [i][k] LDS layout as it is staged; B (k contiguous)
+// is staged as there.  C's loads are issued before the K loop.  Requires K a
+// multiple of KC, 16-byte aligned A and B with even leading dimensions, and
+// an even M; tiles take the XCD-aware order.
+template <int TAG, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nnw_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  typedef typename AccT<F32>::type Acc;
+  __shared__ double sA[2][64 * LDP];
+  __shared__ double sB[2][64 * LDP];
+  int tm, tn;
+  xcd_tile(blockIdx.x, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int ia0 = (wave & 1) * 32, jb0 = (wave >> 1) * 32;
+  const int64_t ib = (int64_t)tm * 64, jb = (int64_t)tn * 64;
+  // C's 16 values of this lane (quadrant element (x, y, r)); rows and
+  // columns outside C read row or column 0 and are not stored
+  double cval[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
+    const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, F32);
+    cval[e] = a.C[(i < a.M ? i : 0) + (j < a.N ? j : 0) * a.ldc];
+  }
+  // staging of A: thread loads one v2d (rows 2 ip, 2 ip + 1) of k rows kr + 8 q
+  const int ip = tid & 31, kr = tid >> 5;
+  const int64_t ia = ib + 2 * ip;
+  const double* ga = a.A + (ia + 1 < a.M ? ia : 0) + (int64_t)kr * a.lda;
+  // staging of B: thread loads one v2d (k pair lq) of columns lc + 16 q
+  const int lc = tid >> 4, lq = tid & 15;
+  const double* gb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = jb + lc + 16 * q;
+    gb[q] = a.B + (j < a.N ? j : 0) * a.ldb + 2 * lq;
+  }
+  Acc acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
+  const int nsl = a.K / KC;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 16) {
+      double xa[2][4], xb[2][4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double* pa = &sA[buf][(ia0 + 16 * t + li) * LDP + kk + 4 * g];
+        const double* pb = &sB[buf][(jb0 + 16 * t + li) * LDP + kk + 4 * g];
+        v2d a0 = *reinterpret_cast<const v2d*>(pa), a1 = *reinterpret_cast<const v2d*>(pa + 2);
+        v2d b0 = *reinterpret_cast<const v2d*>(pb), b1 = *reinterpret_cast<const v2d*>(pb + 2);
+        xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
+        xb[t][0] = b0.x; xb[t][1] = b0.y; xb[t][2] = b1.x; xb[t][3] = b1.y;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+    }
+  };
+  // slab sl's first k (clamped to the last slab: prefetches past the end
+  // reload cached data that is never used)
+  auto koff = [&](int sl) { return (int64_t)std::min(sl, nsl - 1) * KC; };
+  v2d ra0[4], rb0[4], ra1[4], rb1[4];
+#define CQR_NNW_LOAD(RA, RB, K) {                                                 \
+    RA[0] = *reinterpret_cast<const v2d*>(ga + ((K) + 0) * a.lda);               \
+    RB[0] = *reinterpret_cast<const v2d*>(gb[0] + (K));                         \
+    RA[1] = *reinterpret_cast<const v2d*>(ga + ((K) + 8) * a.lda);               \
+    RB[1] = *reinterpret_cast<const v2d*>(gb[1] + (K));                         \
+    RA[2] = *reinterpret_cast<const v2d*>(ga + ((K) + 16) * a.lda);              \
+    RB[2] = *reinterpret_cast<const v2d*>(gb[2] + (K));                         \
+    RA[3] = *reinterpret_cast<const v2d*>(ga + ((K) + 24) * a.lda);              \
+    RB[3] = *reinterpret_cast<const v2d*>(gb[3] + (K));                         \
+  }
+#define CQR_NNW_PUT(BUF, RA, RB) {                                                \
+    _Pragma("unroll")                                                           \
+    for (int q = 0; q < 4; ++q) {                                               \
+      sA[BUF][(2 * ip) * LDP + kr + 8 * q] = RA[q].x;                           \
+      sA[BUF][(2 * ip + 1) * LDP + kr + 8 * q] = RA[q].y;                       \
+      *reinterpret_cast<v2d*>(&sB[BUF][(lc + 16 * q) * LDP + 2 * lq]) = RB[q];  \
+    }                                                                           \
+  }
+  CQR_NNW_LOAD(ra0, rb0, koff(0))
+  CQR_NNW_LOAD(ra1, rb1, koff(1))
+  CQR_NNW_PUT(0, ra0, rb0)
+  __syncthreads();
+  int sl = 0;
+  for (; sl + 2 <= nsl; sl += 2) {
+    CQR_NNW_LOAD(ra0, rb0, koff(sl + 2))
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0);
+    __builtin_amdgcn_sched_barrier(0);
+    CQR_NNW_PUT(1, ra1, rb1)
+    __syncthreads();
+    CQR_NNW_LOAD(ra1, rb1, koff(sl + 3))
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1);
+    __builtin_amdgcn_sched_barrier(0);
+    CQR_NNW_PUT(0, ra0, rb0)
+    __syncthreads();
+  }
+  if (sl < nsl) compute(0);
+#undef CQR_NNW_LOAD
+#undef CQR_NNW_PUT
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
+    const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, F32);
+    if (i < a.M && j < a.N) a.C[i + j * a.ldc] = cval[e] - acc[x][y][r];
+  }
+}
+
+// Operands the LDS-staged long-K update takes (else the register-staged one).
+constexpr bool kUseNnw = false;
+static bool nnw_ok(const NnArgs& a) {
+  return kUseNnw && a.K > NK && a.K % KC == 0 && a.M % 2 == 0 && aligned16(a.A, a.lda) && aligned16(a.B, a.ldb);
+}
+
 template <int TAG, bool F32>
 static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
   if (a.K <= NK)
     hipLaunchKernelGGL((nn1_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (a.nsplit > 1)
     hipLaunchKernelGGL((nn_kernel<true, TAG, F32>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
+  else if (nnw_ok(a))
+    hipLaunchKernelGGL((nnw_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL((nn_kernel<false, TAG, F32>), dim3(a.ntiles, 1), dim3(256), 0, st, a);
 }
