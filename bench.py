@@ -69,7 +69,7 @@ KERNEL_OF = {
 
 
 # the trailing update's kernel for panels wider than 64 columns (K = b > 64)
-LONG_K_UPDATE = "nn_kernel<false, 0, false>"
+LONG_K_UPDATE = "nnw_kernel<0, false>"
 
 
 def model_flops(mp, n, d, b):
@@ -632,11 +632,15 @@ def main():
 
         dom = max((k for k in SINGLE_KERNEL_PHASES if rep[k]["launches"]), key=lambda k: rep[k]["ms"])
         r = rep[dom]
-        if dom in MFMA_PHASES:
+        # the trailing products run on FP32 MFMA in the mixed form, everything else on FP64
+        trail_fp32 = args.precision == "fp32" and dom in ("trailing_product", "trailing_update")
+        mfma_peak = PEAK["fp32_mfma_tflops" if trail_fp32 else "fp64_mfma_tflops"]
+        # the rank-b update moves 16 bytes (read and write of C) per 2b flops:
+        # MFMA-bound when b/8 flop/B exceeds the ridge peak / HBM bandwidth
+        update_mfma = dom == "trailing_update" and b / 8.0 > mfma_peak * 1e3 / PEAK["hbm_gbs"]
+        if dom in MFMA_PHASES or update_mfma:
             ach = r["flops"] / (r["ms"] * 1e-3) / 1e12
-            # the trailing products run on FP32 MFMA in the mixed form, everything else on FP64
-            pk = PEAK["fp32_mfma_tflops" if args.precision == "fp32" and dom == "trailing_product"
-                      else "fp64_mfma_tflops"]
+            pk = mfma_peak
             roof = {"kernel": kernel_of(dom), "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
                     "peak": pk, "unit": "TFLOP/s", "frac": round(ach / pk, 4)}
         else:
