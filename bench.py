@@ -60,16 +60,12 @@ KERNEL_OF = {
     "reproj_product": "tn_lds_kernel<1, false>", "reproj_update": "nn_kernel<*, 1, false>",
     "panel_gram": "tn_lds_kernel<2, false>", "panel_chol": "chol_kernel", "panel_transform": "apply_kernel / nn1_apply_kernel",
     "inpanel_projection": "tn/nn <2, false>",
-    "trailing_product": "tn_lds_kernel<0, false>", "trailing_update": "nn1_kernel<0, false>",
+    "trailing_product": "tn_lds_kernel<0, false>", "trailing_update": "nnw_kernel<0, false>",
     "split_reduce": "tn_reduce_kernel / nn_reduce_kernel", "recover": "line_kernel",
     "postorth": "postorth_kernel", "erase": "erase_kernel", "other": "zero_ints_kernel / fill_zero_kernel",
     "panel_reencode": "encode_rows_kernel (one panel)",
     "solve": "trinv_kernel / gemv_t_kernel / trsv_step_kernel",
 }
-
-
-# the trailing update's kernel for panels wider than 64 columns (K = b > 64)
-LONG_K_UPDATE = "nnw_kernel<0, false>"
 
 
 def model_flops(mp, n, d, b):
@@ -625,8 +621,6 @@ def main():
         # kernel symbol (so rocprofv3's per-kernel average describes the same launches)
         def kernel_of(phase):
             k = KERNEL_OF[phase]
-            if phase == "trailing_update" and b > 64:
-                k = LONG_K_UPDATE      # panels wider than 64 columns: the long-K update kernel
             # the trailing products are the FP32 instances in the mixed form
             return k.replace("<0, false>", "<0, true>") if args.precision == "fp32" else k
 

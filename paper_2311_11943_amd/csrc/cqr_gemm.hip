@@ -975,8 +975,9 @@ __device__ __forceinline__ void nn_mma(Acc (&acc)[4], const double (*sBb)[64 + 1
   }
 }
 
-// C -= A B for K <= 64 (the trailing update: K = b): every load of the tile
-// (C, A, the B slab) is issued before the first product.  The tile loop is
+// C -= A B for K <= 64 (K < 64, or operands nnw_kernel does not take):
+// every load of the tile (C, A, the B slab) is issued before the first
+// product.  The tile loop is
 // grid-strided; launched with one block per tile it runs once.  This form
 // compiles to more registers than the straight-line one (three waves per SIMD
 // instead of four), and measured faster in the factorization: the update's
@@ -1320,8 +1321,8 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
   return a;
 }
 
-// In-place rank-K update C (M x N) -= A (M x K) B (K x N) for K > 64 (the
-// trailing update of panels wider than 64 columns, long re-projections), with
+// In-place rank-K update C (M x N) -= A (M x K) B (K x N) for K >= 64 (the
+// trailing update, long unsplit re-projections), with
 // the product kernel's pipeline: 64 x 64 output tile per block, 4 waves each
 // a 32 x 32 quadrant, both operands staged through LDS in slabs of KC
 // k-values (slab s multiplied while slab s+1 lands in one register set and
@@ -1441,15 +1442,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   }
 }
 
-// Operands the LDS-staged long-K update takes (else the register-staged
-// one): 18-22% faster standalone at K = 128 and 256.
+// Operands the LDS-staged update takes, K >= 64 (else the register-staged
+// kernels): 18-22% faster standalone than the register-staged long-K kernel
+// at K = 128 and 256.  At K = 64 it is ~8% slower alone than nn1_kernel but
+// 1% faster in the factorization, beside the panel chain's kernels.
 static bool nnw_ok(const NnArgs& a) {
-  return a.K > NK && a.K % KC == 0 && a.M % 2 == 0 && aligned16(a.A, a.lda) && aligned16(a.B, a.ldb);
+  return a.K >= NK && a.K % KC == 0 && a.M % 2 == 0 && aligned16(a.A, a.lda) && aligned16(a.B, a.ldb);
 }
 
 template <int TAG, bool F32>
 static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
-  if (a.K <= NK)
+  if (a.K <= NK && !nnw_ok(a))
     hipLaunchKernelGGL((nn1_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (a.nsplit > 1)
     hipLaunchKernelGGL((nn_kernel<true, TAG, F32>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
