@@ -621,6 +621,8 @@ def main():
         # kernel symbol (so rocprofv3's per-kernel average describes the same launches)
         def kernel_of(phase):
             k = KERNEL_OF[phase]
+            if phase == "trailing_update" and b >= 128:
+                k = "nnw16_kernel<0, false>"     # K = b >= 128: the 16-deep-slab form
             # the trailing products are the FP32 instances in the mixed form
             return k.replace("<0, false>", "<0, true>") if args.precision == "fp32" else k
 

@@ -1331,12 +1331,14 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
 // is staged as there.  C's loads are issued before the K loop.  Requires K a
 // multiple of KC, 16-byte aligned A and B with even leading dimensions, and
 // an even M; tiles take the XCD-aware order.
-template <int TAG, bool F32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nnw_kernel(NnArgs a) {
-  if (a.prio) __builtin_amdgcn_s_setprio(2);
+// The body for slabs of SK k-values (32 or 16; LDS row pitch SK + 2).
+template <int TAG, bool F32, int SK>
+__device__ __forceinline__ void nnw_body(const NnArgs& a, double (*sA)[64 * (SK + 2)], double (*sB)[64 * (SK + 2)]) {
   typedef typename AccT<F32>::type Acc;
-  __shared__ double sA[2][64 * LDP];
-  __shared__ double sB[2][64 * LDP];
+  constexpr int LW = SK + 2;         // padded LDS row (doubles)
+  constexpr int NQ = SK / 8;         // v2d loads per thread and operand per slab
+  constexpr int TPC = SK / 2;        // B staging: threads per column (one k pair each)
+  constexpr int CPP = 256 / TPC;     // B staging: columns per pass
   int tm, tn;
   xcd_tile(blockIdx.x, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
@@ -1355,12 +1357,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   const int ip = tid & 31, kr = tid >> 5;
   const int64_t ia = ib + 2 * ip;
   const double* ga = a.A + (ia + 1 < a.M ? ia : 0) + (int64_t)kr * a.lda;
-  // staging of B: thread loads one v2d (k pair lq) of columns lc + 16 q
-  const int lc = tid >> 4, lq = tid & 15;
-  const double* gb[4];
+  // staging of B: thread loads one v2d (k pair lq) of columns lc + CPP q
+  const int lc = tid / TPC, lq = tid % TPC;
+  const double* gb[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t j = jb + lc + 16 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int64_t j = jb + lc + CPP * q;
     gb[q] = a.B + (j < a.N ? j : 0) * a.ldb + 2 * lq;
   }
   Acc acc[2][2];
@@ -1368,15 +1370,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
-  const int nsl = a.K / KC;
+  const int nsl = a.K / SK;
   auto compute = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 16) {
+    for (int kk = 0; kk < SK; kk += 16) {
       double xa[2][4], xb[2][4];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const double* pa = &sA[buf][(ia0 + 16 * t + li) * LDP + kk + 4 * g];
-        const double* pb = &sB[buf][(jb0 + 16 * t + li) * LDP + kk + 4 * g];
+        const double* pa = &sA[buf][(ia0 + 16 * t + li) * LW + kk + 4 * g];
+        const double* pb = &sB[buf][(jb0 + 16 * t + li) * LW + kk + 4 * g];
         v2d a0 = *reinterpret_cast<const v2d*>(pa), a1 = *reinterpret_cast<const v2d*>(pa + 2);
         v2d b0 = *reinterpret_cast<const v2d*>(pb), b1 = *reinterpret_cast<const v2d*>(pb + 2);
         xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
@@ -1392,54 +1394,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   };
   // slab sl's first k (clamped to the last slab: prefetches past the end
   // reload cached data that is never used)
-  auto koff = [&](int sl) { return (int64_t)std::min(sl, nsl - 1) * KC; };
-  v2d ra0[4], rb0[4], ra1[4], rb1[4];
-#define CQR_NNW_LOAD(RA, RB, K) {                                                 \
-    RA[0] = *reinterpret_cast<const v2d*>(ga + ((K) + 0) * a.lda);               \
-    RB[0] = *reinterpret_cast<const v2d*>(gb[0] + (K));                         \
-    RA[1] = *reinterpret_cast<const v2d*>(ga + ((K) + 8) * a.lda);               \
-    RB[1] = *reinterpret_cast<const v2d*>(gb[1] + (K));                         \
-    RA[2] = *reinterpret_cast<const v2d*>(ga + ((K) + 16) * a.lda);              \
-    RB[2] = *reinterpret_cast<const v2d*>(gb[2] + (K));                         \
-    RA[3] = *reinterpret_cast<const v2d*>(ga + ((K) + 24) * a.lda);              \
-    RB[3] = *reinterpret_cast<const v2d*>(gb[3] + (K));                         \
-  }
-#define CQR_NNW_PUT(BUF, RA, RB) {                                                \
-    _Pragma("unroll")                                                           \
-    for (int q = 0; q < 4; ++q) {                                               \
-      sA[BUF][(2 * ip) * LDP + kr + 8 * q] = RA[q].x;                           \
-      sA[BUF][(2 * ip + 1) * LDP + kr + 8 * q] = RA[q].y;                       \
-      *reinterpret_cast<v2d*>(&sB[BUF][(lc + 16 * q) * LDP + 2 * lq]) = RB[q];  \
-    }                                                                           \
-  }
-  CQR_NNW_LOAD(ra0, rb0, koff(0))
-  CQR_NNW_LOAD(ra1, rb1, koff(1))
-  CQR_NNW_PUT(0, ra0, rb0)
+  auto koff = [&](int sl) { return (int64_t)std::min(sl, nsl - 1) * SK; };
+  v2d ra0[NQ], rb0[NQ], ra1[NQ], rb1[NQ];
+  auto load = [&](v2d (&ra)[NQ], v2d (&rb)[NQ], int64_t k) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      ra[q] = *reinterpret_cast<const v2d*>(ga + (k + 8 * q) * a.lda);
+      rb[q] = *reinterpret_cast<const v2d*>(gb[q] + k);
+    }
+  };
+  auto put = [&](int buf, const v2d (&ra)[NQ], const v2d (&rb)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      sA[buf][(2 * ip) * LW + kr + 8 * q] = ra[q].x;
+      sA[buf][(2 * ip + 1) * LW + kr + 8 * q] = ra[q].y;
+      *reinterpret_cast<v2d*>(&sB[buf][(lc + CPP * q) * LW + 2 * lq]) = rb[q];
+    }
+  };
+  load(ra0, rb0, koff(0));
+  load(ra1, rb1, koff(1));
+  put(0, ra0, rb0);
   __syncthreads();
   int sl = 0;
   for (; sl + 2 <= nsl; sl += 2) {
-    CQR_NNW_LOAD(ra0, rb0, koff(sl + 2))
+    load(ra0, rb0, koff(sl + 2));
     __builtin_amdgcn_sched_barrier(0);
     compute(0);
     __builtin_amdgcn_sched_barrier(0);
-    CQR_NNW_PUT(1, ra1, rb1)
+    put(1, ra1, rb1);
     __syncthreads();
-    CQR_NNW_LOAD(ra1, rb1, koff(sl + 3))
+    load(ra1, rb1, koff(sl + 3));
     __builtin_amdgcn_sched_barrier(0);
     compute(1);
     __builtin_amdgcn_sched_barrier(0);
-    CQR_NNW_PUT(0, ra0, rb0)
+    put(0, ra0, rb0);
     __syncthreads();
   }
   if (sl < nsl) compute(0);
-#undef CQR_NNW_LOAD
-#undef CQR_NNW_PUT
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
     const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, F32);
     if (i < a.M && j < a.N) a.C[i + j * a.ldc] = cval[e] - acc[x][y][r];
   }
+}
+
+// 32-deep slabs, two waves per SIMD: the rank-64 trailing update, which runs
+// beside the panel chain (with 16-deep slabs and three waves per SIMD it is
+// faster alone but the step at n = 4096 was 3.8% slower).
+template <int TAG, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nnw_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ double sA[2][64 * (32 + 2)];
+  __shared__ double sB[2][64 * (32 + 2)];
+  nnw_body<TAG, F32, 32>(a, sA, sB);
+}
+
+// 16-deep slabs (37 KB of LDS, 148-164 VGPRs), three waves per SIMD: K >= 128,
+// where the update is MFMA-bound in FP64.  Against the 32-deep form, 9% faster
+// alone at K = 128 and 8% at K = 256, and 4% off the n = 16384 step.
+template <int TAG, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void nnw16_kernel(NnArgs a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ double sA[2][64 * (16 + 2)];
+  __shared__ double sB[2][64 * (16 + 2)];
+  nnw_body<TAG, F32, 16>(a, sA, sB);
 }
 
 // Operands the LDS-staged update takes, K >= 64 (else the register-staged
@@ -1456,6 +1475,8 @@ static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((nn1_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (a.nsplit > 1)
     hipLaunchKernelGGL((nn_kernel<true, TAG, F32>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
+  else if (nnw_ok(a) && a.K >= 2 * NK)
+    hipLaunchKernelGGL((nnw16_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (nnw_ok(a))
     hipLaunchKernelGGL((nnw_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
   else
