@@ -262,6 +262,125 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0);
 }
 
+// The same product with 16-deep slabs (36 KB of LDS, three waves per SIMD),
+// taken by FP32 products with at least two tile rows and two tile columns
+// (the FP32 trailing products of panels wider than 64 columns).  An FP32 MFMA
+// takes fewer cycles than the FP64 one, so the FP32 product waits more on its
+// loads and the third wave hides them (the n = 16384 factorization with FP32
+// updates runs 5% faster); in FP64 the twice as many barriers of the shorter
+// slabs cost more than the extra wave returns (about 1% slower at n = 16384
+// and n = 32768), and FP64 products keep tn_lds_kernel.
+// Thread (lc, lq) stages one v2d (k pair lq) of columns lc + 32 q, q < 2, of
+// each operand per slab; the pipeline, the tile order and the output contract
+// (partials or C, C2) are those of tn_lds_kernel.
+template <int TAG, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void tn16_kernel(TnArgs a) {
+  constexpr int SK = 16, LW = SK + 2, NQ = 2, TPC = SK / 2, CPP = 256 / TPC;
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  typedef typename AccT<F32>::type Acc;
+  __shared__ double sA[2][64 * LW];
+  __shared__ double sB[2][64 * LW];
+  const int tile = blockIdx.x, split = blockIdx.y;
+  const int tm = tile / a.tilesN, tn = tile % a.tilesN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int64_t kb = (int64_t)split * a.kchunk;
+  const int64_t ke = std::min<int64_t>(a.K, kb + a.kchunk);
+  const int lc = tid / TPC, lq = tid % TPC;
+  const double* ga[NQ];
+  const double* gb[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int ia = tm * 64 + lc + CPP * q, jb = tn * 64 + lc + CPP * q;
+    // columns outside the matrix read column 0 and feed only unstored outputs
+    ga[q] = a.A + (int64_t)(ia < a.M ? ia : 0) * a.lda + 2 * lq;
+    gb[q] = a.B + (int64_t)(jb < a.N ? jb : 0) * a.ldb + 2 * lq;
+  }
+  Acc acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
+  const int ia0 = (wave & 1) * 32, jb0 = (wave >> 1) * 32;
+  const int nfull = (int)((ke - kb) / SK);
+  auto compute = [&](int buf) {
+    double xa[2][4], xb[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const double* pa = &sA[buf][(ia0 + 16 * t + li) * LW + 4 * g];
+      const double* pb = &sB[buf][(jb0 + 16 * t + li) * LW + 4 * g];
+      v2d a0 = *reinterpret_cast<const v2d*>(pa), a1 = *reinterpret_cast<const v2d*>(pa + 2);
+      v2d b0 = *reinterpret_cast<const v2d*>(pb), b1 = *reinterpret_cast<const v2d*>(pb + 2);
+      xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
+      xb[t][0] = b0.x; xb[t][1] = b0.y; xb[t][2] = b1.x; xb[t][3] = b1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+  };
+  auto koff = [&](int sl) { return kb + (int64_t)std::min(sl, nfull - 1) * SK; };
+  v2d ra0[NQ], rb0[NQ], ra1[NQ], rb1[NQ];
+  auto load = [&](v2d (&ra)[NQ], v2d (&rb)[NQ], int64_t k) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      ra[q] = *reinterpret_cast<const v2d*>(ga[q] + k);
+      rb[q] = *reinterpret_cast<const v2d*>(gb[q] + k);
+    }
+  };
+  auto put = [&](int buf, const v2d (&ra)[NQ], const v2d (&rb)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      *reinterpret_cast<v2d*>(&sA[buf][(lc + CPP * q) * LW + 2 * lq]) = ra[q];
+      *reinterpret_cast<v2d*>(&sB[buf][(lc + CPP * q) * LW + 2 * lq]) = rb[q];
+    }
+  };
+  if (nfull > 0) {
+    load(ra0, rb0, koff(0));
+    load(ra1, rb1, koff(1));
+    put(0, ra0, rb0);
+    __syncthreads();
+    int sl = 0;
+    for (; sl + 2 <= nfull; sl += 2) {
+      load(ra0, rb0, koff(sl + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      put(1, ra1, rb1);
+      __syncthreads();
+      load(ra1, rb1, koff(sl + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+      put(0, ra0, rb0);
+      __syncthreads();
+    }
+    if (sl < nfull) compute(0);
+  }
+  const int64_t kt = kb + (int64_t)nfull * SK;
+  if (kt < ke) {
+    // partial last slab: masked scalar loads, zero beyond ke
+    const int buf = nfull & 1;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int64_t k = kt + 2 * lq;
+      const double* pa = ga[q] - 2 * lq;
+      const double* pb = gb[q] - 2 * lq;
+      v2d va, vb;
+      va.x = (k < ke) ? pa[k] : 0.0;
+      va.y = (k + 1 < ke) ? pa[k + 1] : 0.0;
+      vb.x = (k < ke) ? pb[k] : 0.0;
+      vb.y = (k + 1 < ke) ? pb[k + 1] : 0.0;
+      *reinterpret_cast<v2d*>(&sA[buf][(lc + CPP * q) * LW + 2 * lq]) = va;
+      *reinterpret_cast<v2d*>(&sB[buf][(lc + CPP * q) * LW + 2 * lq]) = vb;
+    }
+    __syncthreads();
+    compute(buf);
+  }
+  tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0);
+}
+
 // Fallback for operands that are not 16-byte aligned or have odd leading
 // dimensions: direct scalar loads, same tiling and output contract.
 __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
@@ -379,6 +498,10 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
   const dim3 grid(a.ntiles, a.nsplit);
   if (!a.vec) {
     hipLaunchKernelGGL(tn_direct_kernel, grid, dim3(256), 0, st, a);
+    return;
+  }
+  if (a.f32 && a.ntiles / a.tilesN >= 2 && a.tilesN >= 2) {
+    hipLaunchKernelGGL((tn16_kernel<TAG_TRAIL, true>), grid, dim3(256), 0, st, a);
     return;
   }
   if (a.f32) {

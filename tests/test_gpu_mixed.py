@@ -40,6 +40,10 @@ CASES = [
     ("innode_gauss", 512, 8, 2, 64, "in", "gauss", 1.0),
     ("innode_cond1e6", 512, 8, 2, 64, "in", "cond", 1e6),
     ("wide_panel_cond1e10", 512, 4, 2, 128, "out", "cond", 1e10),
+    # panels of two tile rows: the 16-deep FP32 product, also with a ragged
+    # second tile row (b = 120) and a partial last slab (600 coded rows)
+    ("wide_panel_gauss", 512, 4, 2, 128, "out", "gauss", 1.0),
+    ("ragged_wide_panel", 480, 4, 1, 120, "out", "gauss", 1.0),
     ("ragged", 240, 4, 1, 16, "out", "gauss", 1.0),
 ]
 
