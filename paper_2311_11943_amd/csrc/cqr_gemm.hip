@@ -381,6 +381,121 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0);
 }
 
+// Two tile rows per workgroup (512 threads): waves 0-3 compute tile row
+// 2 tp, waves 4-7 tile row 2 tp + 1, both over the same staged slab of B, so
+// B's columns are read once per pair of tile rows.  16-deep slabs (55 KB of
+// LDS).  Thread (lc, lq) stages k pair lq of A's columns lc and lc + 64 and
+// of B's column lc.  Each wave stores its 32 x 32 quadrant of its own 64 x 64
+// tile with the contract of tn_lds_kernel (a missing second tile row of an
+// odd tilesM stages and computes but stores nothing).
+// Taken by FP64 products with at least four tile rows and four tile columns
+// (the trailing products and re-projections of 256-column panels): alone, the
+// K = 49152, 256 x 32768 product runs at 63 TFLOP/s against 55 for
+// tn_lds_kernel.  With two tile rows the halved grid leaves CUs idle (38
+// against 45 TFLOP/s at 128 x 20480), so those keep tn_lds_kernel.
+template <int TAG, bool F32>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) void tn2_kernel(TnArgs a) {
+  constexpr int SK = 16, LW = SK + 2;
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  typedef typename AccT<F32>::type Acc;
+  __shared__ double sA[2][128 * LW];
+  __shared__ double sB[2][64 * LW];
+  const int tp = blockIdx.x / a.tilesN, tn = blockIdx.x % a.tilesN, split = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int h = wave >> 2, w4 = wave & 3;
+  const int tm = 2 * tp + h;
+  const int64_t kb = (int64_t)split * a.kchunk;
+  const int64_t ke = std::min<int64_t>(a.K, kb + a.kchunk);
+  const int lc = tid >> 3, lq = tid & 7;
+  const double* ga[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int ia = tp * 128 + lc + 64 * q;
+    // columns outside the matrix read column 0 and feed only unstored outputs
+    ga[q] = a.A + (int64_t)(ia < a.M ? ia : 0) * a.lda + 2 * lq;
+  }
+  const int jb = tn * 64 + lc;
+  const double* gb = a.B + (int64_t)(jb < a.N ? jb : 0) * a.ldb + 2 * lq;
+  Acc acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = Acc{0, 0, 0, 0};
+  const int ia0 = h * 64 + (w4 & 1) * 32, jb0 = (w4 >> 1) * 32;
+  const int nfull = (int)((ke - kb) / SK);
+  auto compute = [&](int buf) {
+    double xa[2][4], xb[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const double* pa = &sA[buf][(ia0 + 16 * t + li) * LW + 4 * g];
+      const double* pb = &sB[buf][(jb0 + 16 * t + li) * LW + 4 * g];
+      v2d a0 = *reinterpret_cast<const v2d*>(pa), a1 = *reinterpret_cast<const v2d*>(pa + 2);
+      v2d b0 = *reinterpret_cast<const v2d*>(pb), b1 = *reinterpret_cast<const v2d*>(pb + 2);
+      xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
+      xb[t][0] = b0.x; xb[t][1] = b0.y; xb[t][2] = b1.x; xb[t][3] = b1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+  };
+  auto koff = [&](int sl) { return kb + (int64_t)std::min(sl, nfull - 1) * SK; };
+  v2d ra0[2], rb0, ra1[2], rb1;
+  auto load = [&](v2d (&ra)[2], v2d& rb, int64_t k) {
+    ra[0] = *reinterpret_cast<const v2d*>(ga[0] + k);
+    ra[1] = *reinterpret_cast<const v2d*>(ga[1] + k);
+    rb = *reinterpret_cast<const v2d*>(gb + k);
+  };
+  auto put = [&](int buf, const v2d (&ra)[2], const v2d& rb) {
+    *reinterpret_cast<v2d*>(&sA[buf][lc * LW + 2 * lq]) = ra[0];
+    *reinterpret_cast<v2d*>(&sA[buf][(lc + 64) * LW + 2 * lq]) = ra[1];
+    *reinterpret_cast<v2d*>(&sB[buf][lc * LW + 2 * lq]) = rb;
+  };
+  if (nfull > 0) {
+    load(ra0, rb0, koff(0));
+    load(ra1, rb1, koff(1));
+    put(0, ra0, rb0);
+    __syncthreads();
+    int sl = 0;
+    for (; sl + 2 <= nfull; sl += 2) {
+      load(ra0, rb0, koff(sl + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      put(1, ra1, rb1);
+      __syncthreads();
+      load(ra1, rb1, koff(sl + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+      put(0, ra0, rb0);
+      __syncthreads();
+    }
+    if (sl < nfull) compute(0);
+  }
+  const int64_t kt = kb + (int64_t)nfull * SK;
+  if (kt < ke) {
+    // partial last slab: masked scalar loads, zero beyond ke
+    const int buf = nfull & 1;
+    const int64_t k = kt + 2 * lq;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double* p = (q < 2 ? ga[q] : gb) - 2 * lq;
+      v2d v;
+      v.x = (k < ke) ? p[k] : 0.0;
+      v.y = (k + 1 < ke) ? p[k + 1] : 0.0;
+      double* d = q < 2 ? &sA[buf][(lc + 64 * q) * LW + 2 * lq] : &sB[buf][lc * LW + 2 * lq];
+      *reinterpret_cast<v2d*>(d) = v;
+    }
+    __syncthreads();
+    compute(buf);
+  }
+  if (tm < a.ntiles / a.tilesN)
+    tn_store(a, acc, tm * a.tilesN + tn, split, w4, lane, tm * 64 + (w4 & 1) * 32, tn * 64 + jb0);
+}
+
 // Fallback for operands that are not 16-byte aligned or have odd leading
 // dimensions: direct scalar loads, same tiling and output contract.
 __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
@@ -502,6 +617,15 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
   }
   if (a.f32 && a.ntiles / a.tilesN >= 2 && a.tilesN >= 2) {
     hipLaunchKernelGGL((tn16_kernel<TAG_TRAIL, true>), grid, dim3(256), 0, st, a);
+    return;
+  }
+  if (!a.f32 && a.ntiles / a.tilesN >= 4 && a.tilesN >= 4) {
+    const dim3 grid2((unsigned)((a.ntiles / a.tilesN + 1) / 2 * a.tilesN), a.nsplit);
+    switch (tag) {
+      case TAG_TRAIL: hipLaunchKernelGGL((tn2_kernel<TAG_TRAIL, false>), grid2, dim3(512), 0, st, a); break;
+      case TAG_REPROJ: hipLaunchKernelGGL((tn2_kernel<TAG_REPROJ, false>), grid2, dim3(512), 0, st, a); break;
+      default: hipLaunchKernelGGL((tn2_kernel<TAG_PANEL, false>), grid2, dim3(512), 0, st, a); break;
+    }
     return;
   }
   if (a.f32) {

@@ -33,6 +33,10 @@ SHAPES = [
     ("wide_panel", 512, 4, 2, 128, "out", {}),       # recursive panel 64 + 64
     ("odd_panel", 384, 4, 1, 96, "out", {}),         # recursive panel 48 + 48
     ("k4", 256, 8, 4, 32, "out", {}),
+    # panels of four tile rows: the two-tile-row product for the trailing
+    # products and re-projections, also with a 48-row last tile (b = 240)
+    ("panel256", 1024, 4, 1, 256, "out", {}),
+    ("ragged_panel240", 960, 4, 1, 240, "out", {}),
 ]
 
 
