@@ -263,8 +263,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 }
 
 // The same product with 16-deep slabs (36 KB of LDS, three waves per SIMD),
-// taken by FP32 products with at least two tile rows and two tile columns
-// (the FP32 trailing products of panels wider than 64 columns).  An FP32 MFMA
+// taken by FP32 products with two or three tile rows and at least two tile
+// columns (the FP32 trailing products of 128-column panels; from four tile
+// rows on, FP32 products take tn2_kernel).  An FP32 MFMA
 // takes fewer cycles than the FP64 one, so the FP32 product waits more on its
 // loads and the third wave hides them (the n = 16384 factorization with FP32
 // updates runs 5% faster); in FP64 the twice as many barriers of the shorter
@@ -388,11 +389,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // of B's column lc.  Each wave stores its 32 x 32 quadrant of its own 64 x 64
 // tile with the contract of tn_lds_kernel (a missing second tile row of an
 // odd tilesM stages and computes but stores nothing).
-// Taken by FP64 products with at least four tile rows and four tile columns
-// (the trailing products and re-projections of 256-column panels): alone, the
-// K = 49152, 256 x 32768 product runs at 63 TFLOP/s against 55 for
-// tn_lds_kernel.  With two tile rows the halved grid leaves CUs idle (38
-// against 45 TFLOP/s at 128 x 20480), so those keep tn_lds_kernel.
+// Taken by products with at least four tile rows and four tile columns (the
+// trailing products and re-projections of 256-column panels, in FP64 and, for
+// the trailing products, FP32): alone, the K = 49152, 256 x 32768 FP64
+// product runs at 63 TFLOP/s against 55 for tn_lds_kernel.  With two tile
+// rows the halved grid leaves CUs idle (38 against 45 TFLOP/s at
+// 128 x 20480), so those keep tn_lds_kernel or tn16_kernel.
 template <int TAG, bool F32>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) void tn2_kernel(TnArgs a) {
   constexpr int SK = 16, LW = SK + 2;
@@ -596,15 +598,22 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2; a.M2 = M;
   const int tilesM = (M + kTile - 1) / kTile, tilesN = (N + kTile - 1) / kTile;
   const int tiles = tilesM * tilesN;
-  int ns = force_split > 0 ? force_split : pick_split(tiles, K, s.npart);
+  const bool vec = aligned16(A, lda) && aligned16(B, ldb);
+  // two tile rows per workgroup from four tile rows and four tile columns on
+  // (with two or three tile rows the halved grid leaves CUs idle)
+  const bool pair = vec && tilesM >= 4 && tilesN >= 4;
+  // the split count fills the grid of workgroups the product launches
+  const int blocks = pair ? (tilesM + 1) / 2 * tilesN : tiles;
+  int ns = force_split > 0 ? force_split : pick_split(blocks, K, s.npart);
   while (ns > 1 && (int64_t)ns * tiles > s.npart) --ns;
   int64_t kchunk = (K + ns - 1) / ns;
   kchunk = (kchunk + KC - 1) / KC * KC;
   ns = (int)((K + kchunk - 1) / kchunk);
   a.M = M; a.N = N; a.K = K; a.kchunk = kchunk; a.nsplit = ns; a.tilesN = tilesN; a.ntiles = tiles;
   a.part = s.part;
-  a.vec = aligned16(A, lda) && aligned16(B, ldb);
+  a.vec = vec;
   a.f32 = f32 && a.vec;     // the FP32 form exists for the LDS-staged kernel
+  a.pair = pair;
   return a;
 }
 
@@ -615,17 +624,21 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
     hipLaunchKernelGGL(tn_direct_kernel, grid, dim3(256), 0, st, a);
     return;
   }
-  if (a.f32 && a.ntiles / a.tilesN >= 2 && a.tilesN >= 2) {
-    hipLaunchKernelGGL((tn16_kernel<TAG_TRAIL, true>), grid, dim3(256), 0, st, a);
-    return;
-  }
-  if (!a.f32 && a.ntiles / a.tilesN >= 4 && a.tilesN >= 4) {
+  if (a.pair) {
     const dim3 grid2((unsigned)((a.ntiles / a.tilesN + 1) / 2 * a.tilesN), a.nsplit);
+    if (a.f32) {
+      hipLaunchKernelGGL((tn2_kernel<TAG_TRAIL, true>), grid2, dim3(512), 0, st, a);
+      return;
+    }
     switch (tag) {
       case TAG_TRAIL: hipLaunchKernelGGL((tn2_kernel<TAG_TRAIL, false>), grid2, dim3(512), 0, st, a); break;
       case TAG_REPROJ: hipLaunchKernelGGL((tn2_kernel<TAG_REPROJ, false>), grid2, dim3(512), 0, st, a); break;
       default: hipLaunchKernelGGL((tn2_kernel<TAG_PANEL, false>), grid2, dim3(512), 0, st, a); break;
     }
+    return;
+  }
+  if (a.f32 && a.ntiles / a.tilesN >= 2 && a.tilesN >= 2) {
+    hipLaunchKernelGGL((tn16_kernel<TAG_TRAIL, true>), grid, dim3(256), 0, st, a);
     return;
   }
   if (a.f32) {

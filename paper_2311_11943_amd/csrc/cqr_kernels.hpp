@@ -92,6 +92,7 @@ struct TnArgs {
   int vec;            // both operands 16-byte aligned with even leading dimensions
   int f32;            // FP32 products (operands rounded), FP32 accumulation
   int prio;           // raise the waves' issue priority (panel-chain products)
+  int pair;           // two tile rows per 512-thread workgroup (tn2_kernel)
 };
 
 // Choose the split of C = A^T B (stored to C; rows below M2 -- all rows

@@ -44,6 +44,8 @@ CASES = [
     # second tile row (b = 120) and a partial last slab (600 coded rows)
     ("wide_panel_gauss", 512, 4, 2, 128, "out", "gauss", 1.0),
     ("ragged_wide_panel", 480, 4, 1, 120, "out", "gauss", 1.0),
+    # four tile rows: the FP32 form of the two-tile-row product
+    ("panel256", 1024, 4, 1, 256, "out", "gauss", 1.0),
     ("ragged", 240, 4, 1, 16, "out", "gauss", 1.0),
 ]
 
