@@ -624,13 +624,10 @@ def main():
             if phase == "trailing_update" and b >= 128:
                 k = "nnw16_kernel<0, false>"     # K = b >= 128: the 16-deep-slab form
             if phase == "trailing_product" and b > 64:
-                # panels of several tile rows: two tile rows per workgroup from
-                # four tile rows on, else the 16-deep form in FP32 (the last few
-                # products, with fewer tile columns, keep tn_lds_kernel)
-                if b > 192:
-                    k = "tn2_kernel<0, false>"
-                elif args.precision == "fp32":
-                    return "tn16_kernel<0, true>"
+                # panels of several tile rows: two tile rows per workgroup (the
+                # last few products, with fewer tile columns, keep the one-tile
+                # kernels)
+                k = "tn2_kernel<0, false>"
             # the trailing products are the FP32 instances in the mixed form
             return k.replace("<0, false>", "<0, true>") if args.precision == "fp32" else k
 

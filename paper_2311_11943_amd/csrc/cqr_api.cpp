@@ -553,7 +553,9 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   maxTiles = std::max(maxTiles, tiles(b, N - b));          // trailing update
   maxTiles = std::max(maxTiles, tiles(n - b, b));          // re-projection
   maxTiles = std::max(maxTiles, tiles(b, b));              // within-panel projection, Gram
-  p->npart = std::max<int64_t>(1024, maxTiles);
+  // four partial tiles per output tile: large products split up to ~1280
+  // workgroups (32 KB per partial tile)
+  p->npart = std::max<int64_t>(1024, 4 * maxTiles);
   p->nS = std::max<int64_t>(n * b, (int64_t)kLeaf * kLeaf);   // S with the fused Gram rows: c1 x b, c1 <= n
   size_t off = 256;
   p->off_part = off;  off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);

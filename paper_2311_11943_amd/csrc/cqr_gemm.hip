@@ -263,9 +263,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 }
 
 // The same product with 16-deep slabs (36 KB of LDS, three waves per SIMD),
-// taken by FP32 products with two or three tile rows and at least two tile
-// columns (the FP32 trailing products of 128-column panels; from four tile
-// rows on, FP32 products take tn2_kernel).  An FP32 MFMA
+// taken by FP32 products with at least two tile rows and two or three tile
+// columns (the last trailing products of wider panels; with four or more tile
+// columns, FP32 products take tn2_kernel).  An FP32 MFMA
 // takes fewer cycles than the FP64 one, so the FP32 product waits more on its
 // loads and the third wave hides them (the n = 16384 factorization with FP32
 // updates runs 5% faster); in FP64 the twice as many barriers of the shorter
@@ -389,12 +389,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // of B's column lc.  Each wave stores its 32 x 32 quadrant of its own 64 x 64
 // tile with the contract of tn_lds_kernel (a missing second tile row of an
 // odd tilesM stages and computes but stores nothing).
-// Taken by products with at least four tile rows and four tile columns (the
-// trailing products and re-projections of 256-column panels, in FP64 and, for
-// the trailing products, FP32): alone, the K = 49152, 256 x 32768 FP64
-// product runs at 63 TFLOP/s against 55 for tn_lds_kernel.  With two tile
-// rows the halved grid leaves CUs idle (38 against 45 TFLOP/s at
-// 128 x 20480), so those keep tn_lds_kernel or tn16_kernel.
+// Taken by products with at least two tile rows and four tile columns (the
+// trailing products of panels wider than 64 columns, in FP64 and FP32, the
+// re-projections of 256-column panels): alone, the K = 49152, 256 x 32768
+// FP64 product runs at 63 TFLOP/s against 55 for tn_lds_kernel, and the
+// 128 x 20480 product with depth 24576 at 55 against 52 (each with the split
+// count that fills its grid).
 template <int TAG, bool F32>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) void tn2_kernel(TnArgs a) {
   constexpr int SK = 16, LW = SK + 2;
@@ -581,10 +581,13 @@ static bool aligned16(const void* p, int64_t ld) {
 }
 
 static int pick_split(int tiles, int64_t K, int64_t cap) {
-  // at most 512 blocks (two resident per CU, so one wave of blocks: a few
-  // blocks over that run as a second wave and cost ~16% at 79 tiles); each
-  // split keeps at least 256 rows (8 slabs)
-  int want = std::max(1, 512 / std::max(1, tiles));
+  // Below 256 workgroups: at most 512 (two resident per CU, so one wave of
+  // workgroups; a few over that run as a second wave and cost ~16% at 79
+  // tiles).  From 256 on, splits up to ~1280 workgroups: the shorter
+  // workgroups even out the last wave (alone, the 128 x 20480 product with
+  // depth 24576 runs at 51.6 TFLOP/s with two splits against 44.3 with one).
+  // Each split keeps at least 256 rows (8 slabs).
+  int want = tiles >= 256 ? (1280 + tiles - 1) / tiles : std::max(1, 512 / std::max(1, tiles));
   int64_t maxs = std::max<int64_t>(1, K / 256);
   int ns = (int)std::min<int64_t>(want, maxs);
   while (ns > 1 && (int64_t)ns * tiles > cap) --ns;
@@ -599,9 +602,9 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   const int tilesM = (M + kTile - 1) / kTile, tilesN = (N + kTile - 1) / kTile;
   const int tiles = tilesM * tilesN;
   const bool vec = aligned16(A, lda) && aligned16(B, ldb);
-  // two tile rows per workgroup from four tile rows and four tile columns on
-  // (with two or three tile rows the halved grid leaves CUs idle)
-  const bool pair = vec && tilesM >= 4 && tilesN >= 4;
+  // two tile rows per workgroup from two tile rows and four tile columns on
+  // (with fewer tile columns the re-projections on the panel chain slow down)
+  const bool pair = vec && tilesM >= 2 && tilesN >= 4;
   // the split count fills the grid of workgroups the product launches
   const int blocks = pair ? (tilesM + 1) / 2 * tilesN : tiles;
   int ns = force_split > 0 ? force_split : pick_split(blocks, K, s.npart);
