@@ -16,9 +16,10 @@ Everything is numpy float64 and follows the paper's steps in its notation:
                 Q-factor checksum generator; in-node variant with K rows);
                 R side: any MDS generator, with the storing column excluded for
                 in-node storage (Construction "In-Node Systematic MDS Coding")
-  factor        PBMGS (appendix algorithm PBMGS / sequential BMGS): for each
-                panel of width b, ICGS/CGS2 on the panel, then R_bar = Qbar^T Q_t
-                and Q_t -= Qbar R_bar on every column right of the panel
+  factor        blocked Gram-Schmidt (algorithms PBMGS / BMGS): per panel of
+                width b, an orthonormal basis of the panel (ICGS/CGS2/MGS), then
+                every column right of the panel projected onto the orthogonal
+                complement of that basis, the coefficients recorded in R
   recover       erased blocks decoded from surviving blocks and checksums by
                 solving the small G_hat system (proof of the recovery-overhead
                 lemma), then lost checksum blocks re-encoded
@@ -262,17 +263,20 @@ def panel_cgs2(P: np.ndarray, Rpp: np.ndarray, reorth: str = "always", eta: floa
 
 
 def panel_mgs(P: np.ndarray, Rpp: np.ndarray) -> int:
-    """Sequential modified Gram-Schmidt restricted to the panel (the paper's
-    MGS algorithm, which its experiments used in place of ICGS)."""
+    """Modified Gram-Schmidt restricted to the panel (the paper's sequential MGS,
+    which its experiments used in place of ICGS).
+
+    Each new basis vector q_i = u_i / ||u_i|| is removed at once from every
+    column to its right by the rank-one projection I - q_i q_i^T, so a column
+    has been projected against q_0 .. q_{j-1} one vector at a time by the time
+    it is normalised.  The coefficients q_i^T u_j form row i of the panel's R."""
     b = P.shape[1]
     for i in range(b):
-        r = np.linalg.norm(P[:, i])
-        Rpp[i, i] = r
-        P[:, i] /= r
-        for j in range(i + 1, b):
-            rij = P[:, i] @ P[:, j]
-            Rpp[i, j] = rij
-            P[:, j] -= rij * P[:, i]
+        Rpp[i, i] = np.linalg.norm(P[:, i])
+        P[:, i] /= Rpp[i, i]
+        if i + 1 < b:
+            coef, P[:, i + 1:] = _project_out(P[:, i:i + 1], P[:, i + 1:])
+            Rpp[i, i + 1:] = coef[0]
     return 0
 
 
@@ -288,37 +292,52 @@ class FactorOptions:
     eta: float = ETA_DGKS
 
 
-def factor_panels(Q: np.ndarray, R: np.ndarray, n: int, k0: int, k1: int, opt: FactorOptions) -> dict:
-    """Run panels k0 .. k1-1 of the blocked Gram-Schmidt on Q (m' x N, in place,
-    starts as A~) accumulating R (n x N).
+def _project_out(basis: np.ndarray, X: np.ndarray):
+    """Split X into its part in the span of an orthonormal basis and the rest:
+    X = basis C + X_perp with C = basis^T X.  Returns (C, X_perp)."""
+    C = basis.T @ X
+    return C, X - basis @ C
 
-    Panel k covers columns [kb, (k+1)b).  Steps per panel:
-      (optional) left re-projection: S = Q[:, :kb]^T P, P -= Q[:, :kb] S,
-                 R[:kb, panel] += S;
-      panel ICGS/CGS2/MGS -> R[panel, panel];
-      if columns remain right of the panel (systematic or checksum):
-                 R_bar = Qbar^T Q_t,  R[panel, right] = R_bar,  Q_t -= Qbar R_bar."""
+
+def panel_factor(P: np.ndarray, opt: "FactorOptions"):
+    """Orthonormal basis of the panel's columns and the upper-triangular
+    factor with P = basis R_pp (positive diagonal), by the panel method chosen.
+    Returns (basis, R_pp, number of reorthogonalised columns)."""
+    P = P.copy()
+    Rpp = np.zeros((P.shape[1], P.shape[1]))
+    if opt.panel == "mgs":
+        nre = panel_mgs(P, Rpp)
+    else:
+        nre = panel_cgs2(P, Rpp, "always" if opt.panel == "cgs2" else "dgks", opt.eta)
+    return P, Rpp, nre
+
+
+def factor_panels(Q: np.ndarray, R: np.ndarray, n: int, k0: int, k1: int, opt: FactorOptions) -> dict:
+    """Panels k0 .. k1-1 of the blocked Gram-Schmidt (algorithms BMGS / PBMGS)
+    on the iteration state Q (m' x N, in place; A~ at the start), accumulating
+    the coefficients in R (n x N).
+
+    Panel k holds columns [kb, (k+1)b).  Its columns are first made orthogonal
+    to every earlier basis vector (the optional left re-projection: the part of
+    the panel in the span of Q[:, :kb] is removed and its coefficients are
+    added to R[:kb, panel]); the panel method then gives an orthonormal basis
+    of the panel and its triangular factor R[panel, panel]; finally every
+    column to the right -- systematic or carried checksum column -- is replaced
+    by its component orthogonal to the new basis, the coefficients of the
+    removed part going to R[panel, right].  Every step is a column operation
+    on the encoded matrix, which is what keeps its checksum rows valid."""
     b = opt.b
     N = Q.shape[1]
     nre = 0
     for k in range(k0, k1):
-        c0, c1 = k * b, (k + 1) * b
+        panel, right = slice(k * b, (k + 1) * b), slice((k + 1) * b, N)
         if opt.reproject and k > 0:
-            S = Q[:, :c0].T @ Q[:, c0:c1]
-            Q[:, c0:c1] -= Q[:, :c0] @ S
-            R[:c0, c0:c1] += S
-        P = Q[:, c0:c1].copy()
-        Rpp = np.zeros((b, b))
-        if opt.panel == "mgs":
-            panel_mgs(P, Rpp)
-        else:
-            nre += panel_cgs2(P, Rpp, "always" if opt.panel == "cgs2" else "dgks", opt.eta)
-        Q[:, c0:c1] = P
-        R[c0:c1, c0:c1] = Rpp
-        if c1 < N:
-            Rbar = P.T @ Q[:, c1:]
-            R[c0:c1, c1:] = Rbar
-            Q[:, c1:] -= P @ Rbar
+            S, Q[:, panel] = _project_out(Q[:, :k * b], Q[:, panel])
+            R[:k * b, panel] += S
+        Q[:, panel], R[panel, panel], nr = panel_factor(Q[:, panel], opt)
+        nre += nr
+        if (k + 1) * b < N:
+            R[panel, right], Q[:, right] = _project_out(Q[:, panel], Q[:, right])
     return {"reorth_columns": nre}
 
 

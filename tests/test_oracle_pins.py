@@ -329,6 +329,64 @@ def test_in_node_tolerates_f_failures(pr, K):
         assert np.abs(R - R0).max() < 1e-10 * np.abs(R0).max()
 
 
+def _storers(lay):
+    """From the oracle's node_blocks alone: the grid row of the node that holds
+    Q-checksum block row k in each block column, and the grid column of the
+    node that holds R-checksum block column k in each block row."""
+    qrow, rcol = {}, {}
+    for i in range(lay.pr):
+        for j in range(lay.pc):
+            qb, rb = lay.node_blocks((i, j))
+            for I, J in qb:
+                if I >= lay.pr and J == j:
+                    qrow.setdefault(I - lay.pr, set()).add(i)
+            for I, J in rb:
+                if J >= lay.pc and I == i:
+                    rcol.setdefault(J - lay.pc, set()).add(j)
+    return qrow, rcol
+
+
+@pytest.mark.parametrize("P,K", [(8, 2), (8, 3), (16, 8), (4, 4), (6, 9), (5, 7), (3, 1)])
+def test_in_node_placement_is_load_balanced(P, K):
+    """Definition of the load-balanced in-node distribution: of the P nodes of a
+    code line, a_bar = K - P floor(K/P) hold ceil(K/P) checksum blocks and the
+    other P - a_bar hold floor(K/P); every checksum block sits on exactly one
+    node of the line, and in the same position in every line (so one
+    generator describes the code of every block row and column)."""
+    lay = oc.Layout(4 * P, 4 * P, P, P, K, K, oc.IN_NODE)
+    qrow, rcol = _storers(lay)
+    for where in (qrow, rcol):
+        assert sorted(where) == list(range(K))
+        assert all(len(nodes) == 1 for nodes in where.values())      # one storer, same in every line
+        count = [0] * P
+        for nodes in where.values():
+            count[next(iter(nodes))] += 1
+        a_bar = K - P * (K // P)
+        assert sorted(count, reverse=True) == [-(-K // P)] * a_bar + [K // P] * (P - a_bar)
+
+
+@pytest.mark.parametrize("P,K", [(8, 2), (16, 8), (4, 2), (6, 3)])
+def test_in_node_r_code_excludes_its_storer(P, K):
+    """In-node systematic MDS construction: the checksum stored on node s sums
+    the data of every other node of its line and not s's own,
+    C_k = sum_{t != s_k} g~[t, k] D_t; the storer s_k is found from the
+    placement alone.  The Q side keeps the full sum (its generator has no zero:
+    G~_1 = -1/2 V~ V~^T and V~ are dense), the alternative that the paper's
+    remark on in-node storage allows."""
+    lay = oc.Layout(4 * P, 4 * P, P, P, K, K, oc.IN_NODE)
+    _, rcol = _storers(lay)
+    raw = synth.r_generator_draws(P, K, 3) + 0.5          # strictly positive raw entries
+    g = oc.r_generator(raw, oc.IN_NODE)
+    for k in range(K):
+        s_k = next(iter(rcol[k]))
+        assert g[s_k, k] == 0.0
+        assert all(g[t, k] == raw[t, k] for t in range(P) if t != s_k)
+    gv = oc.q_generator(synth.q_generator_draws(K, P, 3) + 0.5)
+    assert (gv != 0.0).all()
+    # out of node nothing is excluded
+    assert (oc.r_generator(raw, oc.OUT_OF_NODE) == raw).all()
+
+
 def test_reverse_diagonal_storm_recovers():
     pr, K = 8, 4
     n = 64
