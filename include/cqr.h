@@ -44,24 +44,45 @@ typedef enum {
   CQR_ESINGULAR = 3,       /* the small generator submatrix to invert is numerically singular */
   CQR_EHIP = 4,            /* a HIP runtime call failed (launch, copy) */
   CQR_ENOMEM = 5,          /* workspace too small / host allocation failed */
-  CQR_EBREAKDOWN = 6       /* panel Gram matrix not positive definite (rank-deficient input) */
+  CQR_EBREAKDOWN = 6       /* a panel column is zero after projection (rank-deficient input) */
 } cqr_status;
 
 typedef enum { CQR_OUT_OF_NODE = 0, CQR_IN_NODE = 1 } cqr_storage;
 
-/* Arithmetic of the trailing-update products R_bar = Qbar^T Q_t and
- * Q_t -= Qbar R_bar.  CQR_TRAIL_FP32: operands rounded to FP32, products and
- * accumulation on FP32 MFMA, results stored back into the FP64 arrays.  The
- * re-projection (the second Gram-Schmidt pass), the panel factorization, the
- * recovery solve and the post-orthogonalization stay FP64 in every mode, so
- * the FP64 second pass wins back the orthogonality the FP32 first pass loses.
- * In CQR_TRAIL_FP32 each panel's checksum rows are re-derived from its
- * systematic rows in FP64 before the panel is factored (FP32 rounding is not
- * linear, so the updates alone would let Q_2 = G_v Q_1 drift by about
- * u32 kappa(A)); finished columns of Q~ then keep the row-checksum relation to
- * FP64 rounding, while unfinished columns and the R checksum columns hold it to
- * FP32 rounding of the updates.  CQR_TRAIL_BF16X3 is reserved. */
+/* Arithmetic of the trailing update's coefficient product R_bar = Qbar^T Q_t
+ * (not in the paper: a growth direction).  CQR_FP64: everything in FP64.
+ * CQR_TRAIL_FP32: R_bar (and the early update's Qbar1^T Q_t) on FP32 MFMA,
+ * operands rounded to FP32, FP32 sums over 16 k-values and FP64 sums across
+ * them.  In every mode the column operations
+ * on A~ -- the rank-b update Q_t -= Qbar R_bar, the re-projection and the
+ * panel factorization -- run in FP64 with the coefficients R records, so the
+ * checksum rows are carried (Q_2 = G_v Q_1 to FP64 rounding, nothing is
+ * re-encoded) and A~ = Q~ R holds to FP64 rounding; the FP64 re-projection of
+ * the next panels removes what the reduced-precision R_bar leaves behind.  The
+ * R-side relation R_2 = R_1 G_h holds for finished columns to FP64 rounding
+ * and for unfinished columns to the accuracy of R_bar, which bounds the error
+ * of R blocks decoded mid-factorization.  CQR_TRAIL_BF16X3 is reserved. */
 typedef enum { CQR_FP64 = 0, CQR_TRAIL_FP32 = 1, CQR_TRAIL_BF16X3 = 2 } cqr_precision;
+
+/* How each panel is orthogonalised (appendix algorithms PBMGS, CGS,
+ * sequential MGS; ICGS in the PBMGS listing).  Every mode is a column
+ * operation on the panel, so the checksum rows are carried through it.
+ *   CQR_PANEL_CHOLQR2 (default): two Cholesky-QR passes, the block form of
+ *     CGS2 (a Gram product and a 64 x 64 Cholesky per pass).  A pass whose
+ *     Cholesky pivot falls to 1e-14 of its diagonal entry (a column within
+ *     1e-7 rad of the span of the others) hands the panel to the column-wise
+ *     CGS2 below; coded_qr_ws_panel_fallbacks counts such panels.
+ *   CQR_PANEL_CGS2: column-wise classical Gram-Schmidt, every column
+ *     projected twice against the finished columns of its panel.
+ *   CQR_PANEL_ICGS: the same with the second projection only when the first
+ *     left less than icgs_eta of the column's norm (the Daniel-Gragg-
+ *     Kaufman-Stewart test, a reading of the paper's unstated criterion).
+ *   CQR_PANEL_MGS: the paper's sequential modified Gram-Schmidt within the
+ *     panel (its experiments' choice; with reproject = 0 the paper's method).
+ * The column-wise modes run one workgroup per panel leaf of up to 64 columns
+ * with FP64 norms and wavefront reductions; wider panels are split in halves,
+ * the right half projected twice against the left one. */
+typedef enum { CQR_PANEL_CHOLQR2 = 0, CQR_PANEL_CGS2 = 1, CQR_PANEL_ICGS = 2, CQR_PANEL_MGS = 3 } cqr_panel;
 
 typedef struct {
   int64_t m, n;        /* A is m x n; the paper's problem is square (m == n) */
@@ -83,6 +104,8 @@ typedef struct {
                           hold four streams, as many as a device has hardware
                           queues by default, so their streams may share queues and
                           lose the overlap.  0: everything on the caller's stream */
+  int32_t panel;       /* cqr_panel */
+  double icgs_eta;     /* CQR_PANEL_ICGS threshold in (0, 1]; 0 selects 1/sqrt(2) */
 } cqr_config;
 
 typedef struct cqr_plan_s* cqr_plan;
@@ -100,7 +123,7 @@ typedef struct cqr_plan_s* cqr_plan;
  *   Requires: K_v <= p_r/2 when K_v > 0 (post-orthogonalization construction);
  *   m % p_r == n % p_c == n % p_r == 0; b | n; p_r, p_c <= 32; K_v, K_h <= 8;
  *   p_r + K_v <= 32 and p_c + K_h <= 32; precision is CQR_FP64 or
- *   CQR_TRAIL_FP32.
+ *   CQR_TRAIL_FP32; panel is a cqr_panel; 0 <= icgs_eta <= 1.
  * Returns CQR_EINVAL on any violated condition; *out is then NULL.
  */
 cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, const double* gh,
@@ -110,6 +133,18 @@ void coded_qr_plan_destroy(cqr_plan plan);
 /* Copy the plan's generators to host buffers: gv (K_v x p_r, row-major),
  * gh (p_c x K_h, row-major, exclusion zeros applied).  Either may be NULL. */
 cqr_status coded_qr_plan_generators(cqr_plan plan, double* gv, double* gh);
+
+/* Placement of the checksum blocks (host outputs; either may be NULL).
+ * qrow (K_v entries): the grid row whose nodes store Q-checksum block row k,
+ * the same in every block column; rcol (K_h entries): the grid column whose
+ * nodes store R-checksum block column k, the same in every block row.
+ * In-node storage (load-balanced distribution: of the p_r nodes of a grid
+ * column, K_v - p_r floor(K_v/p_r) hold ceil(K_v/p_r) checksum blocks and the
+ * rest floor(K_v/p_r)): qrow[k] = k mod p_r, rcol[k] = k mod p_c, and the R
+ * code excludes the storer, G~_h[rcol[k], k] = 0.  Out-of-node storage:
+ * checksum nodes of their own, qrow[k] = p_r + k and rcol[k] = p_c + k on the
+ * extended grid. */
+cqr_status coded_qr_plan_placement(cqr_plan plan, int32_t* qrow, int32_t* rcol);
 
 /* Failures per grid row / column the plan's code tolerates (out-of-node: K;
  * in-node: largest f with f + f*ceil(f/(p_r-f)) <= K, the theorem on the
@@ -159,8 +194,15 @@ cqr_status coded_qr_factor(cqr_plan plan, double* At, int64_t ldat, double* R, i
                            hipStream_t stream);
 
 /* Blocking: wait for `stream`, then return the breakdown flag stored in ws
- * (0 = none, else 1 + the panel index of the first breakdown) in *info (host). */
+ * (0 = none, else 1 + the index of the first panel with a zero column after
+ * projection, i.e. exactly rank-deficient input) in *info (host); returns
+ * CQR_EBREAKDOWN when it is set. */
 cqr_status coded_qr_ws_info(cqr_plan plan, const void* ws, hipStream_t stream, int32_t* info);
+
+/* Blocking: wait for `stream`, then return in *count (host) how many panel
+ * leaves since the last call with panel_begin == 0 were orthogonalised by
+ * the column-wise CGS2 fallback after a Cholesky-QR breakdown. */
+cqr_status coded_qr_ws_panel_fallbacks(cqr_plan plan, const void* ws, hipStream_t stream, int32_t* count);
 
 /*
  * Fail-stop failure simulation: set every block held by the listed nodes to NaN
@@ -285,7 +327,7 @@ cqr_status coded_qr_solve_backward(cqr_plan plan, const double* Qpost, int64_t l
  * panels), 7 trailing product (R_bar = Qbar^T Q_t), 8 trailing update
  * (Q_t -= Qbar R_bar), 9 reduction of split-product partial tiles, 10 recovery,
  * 11 post-orthogonalization, 12 erase, 13 other (workspace/R initialisation),
- * 14 per-panel checksum re-encode (CQR_TRAIL_FP32 only), 15 coded solve,
+ * 14 column-wise panel (CQR_PANEL_CGS2 / ICGS / MGS), 15 coded solve,
  * 16 adjoint (coded_qr_backward, coded_qr_solve_backward).
  * coded_qr_profile_read returns, for `phase`, the summed event time (ms), the
  * number of launches and the summed flops / bytes (host outputs; may be NULL).

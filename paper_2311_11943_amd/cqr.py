@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcqr.so")
 CQR_OK, CQR_EINVAL, CQR_ENOTRECOVERABLE, CQR_ESINGULAR, CQR_EHIP, CQR_ENOMEM, CQR_EBREAKDOWN = range(7)
 CQR_OUT_OF_NODE, CQR_IN_NODE = 0, 1
 CQR_FP64, CQR_TRAIL_FP32, CQR_TRAIL_BF16X3 = 0, 1, 2
+CQR_PANEL_CHOLQR2, CQR_PANEL_CGS2, CQR_PANEL_ICGS, CQR_PANEL_MGS = 0, 1, 2, 3
 
 EXPORTS = [
     "coded_qr_plan_create", "coded_qr_plan_destroy", "coded_qr_plan_generators", "coded_qr_plan_ftol",
@@ -27,11 +28,12 @@ EXPORTS = [
     "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name", "coded_qr_solve",
     "coded_qr_solve_workspace_bytes", "coded_qr_backward", "coded_qr_backward_workspace_bytes",
     "coded_qr_solve_backward", "coded_qr_solve_backward_workspace_bytes", "coded_qr_plan_r_rows",
+    "coded_qr_plan_placement", "coded_qr_ws_panel_fallbacks",
 ]
 
 PHASES = ["encode", "reproj_product", "reproj_update", "panel_gram", "panel_chol", "panel_transform",
           "inpanel_projection", "trailing_product", "trailing_update", "split_reduce", "recover", "postorth",
-          "erase", "other", "panel_reencode", "solve", "adjoint"]
+          "erase", "other", "panel_colwise", "solve", "adjoint"]
 
 
 class CqrError(RuntimeError):
@@ -47,7 +49,7 @@ class cqr_config(ctypes.Structure):
                 ("kv", ctypes.c_int32), ("kh", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("b", ctypes.c_int32),
                 ("reproject", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32)]
+                ("lookahead", ctypes.c_int32), ("panel", ctypes.c_int32), ("icgs_eta", ctypes.c_double)]
 
 
 def _load() -> ctypes.CDLL:
@@ -65,10 +67,12 @@ def _load() -> ctypes.CDLL:
         "coded_qr_plan_destroy": (None, [P]),
         "coded_qr_plan_generators": (I32, [P, P, P]),
         "coded_qr_plan_ftol": (I32, [P]),
+        "coded_qr_plan_placement": (I32, [P, P, P]),
         "coded_qr_workspace_bytes": (SZ, [P]),
         "coded_qr_encode": (I32, [P, D, I64, V]),
         "coded_qr_factor": (I32, [P, D, I64, D, I64, I32, I32, D, SZ, V]),
         "coded_qr_ws_info": (I32, [P, D, V, ctypes.POINTER(ctypes.c_int32)]),
+        "coded_qr_ws_panel_fallbacks": (I32, [P, D, V, ctypes.POINTER(ctypes.c_int32)]),
         "coded_qr_erase": (I32, [P, D, I64, D, I64, P, I32, V]),
         "coded_qr_recover": (I32, [P, D, I64, D, I64, P, I32, V]),
         "coded_qr_postorth": (I32, [P, D, I64, D, I64, D, I64, D, I64, I32, V]),
@@ -162,10 +166,12 @@ class Config:
     reproject: int = 1
     precision: int = CQR_FP64
     lookahead: int = 1
+    panel: int = CQR_PANEL_CHOLQR2
+    icgs_eta: float = 0.0
 
     def c(self) -> cqr_config:
         return cqr_config(self.m, self.n, self.pr, self.pc, self.kv, self.kh, self.storage, self.b,
-                          self.reproject, self.precision, self.lookahead)
+                          self.reproject, self.precision, self.lookahead, self.panel, self.icgs_eta)
 
     @property
     def bs(self):
@@ -212,6 +218,17 @@ def coded_qr_plan_generators(plan: int, cfg: Config):
     return gv, gh
 
 
+def coded_qr_plan_placement(plan: int, cfg: Config):
+    """(qrow, rcol): the grid row storing each Q-checksum block row and the grid
+    column storing each R-checksum block column (extended-grid indices for
+    out-of-node storage)."""
+    qrow = np.zeros(max(cfg.kv, 1), dtype=np.int32)
+    rcol = np.zeros(max(cfg.kh, 1), dtype=np.int32)
+    _check(LIB.coded_qr_plan_placement(ctypes.c_void_p(plan), qrow.ctypes.data_as(ctypes.c_void_p),
+                                       rcol.ctypes.data_as(ctypes.c_void_p)), "coded_qr_plan_placement")
+    return qrow[:cfg.kv].copy(), rcol[:cfg.kh].copy()
+
+
 def coded_qr_plan_ftol(plan: int) -> int:
     return LIB.coded_qr_plan_ftol(ctypes.c_void_p(plan))
 
@@ -239,6 +256,14 @@ def coded_qr_ws_info(plan: int, ws, stream=None) -> tuple[int, int]:
 def _nodes(nodes):
     arr = np.ascontiguousarray(np.array(nodes, dtype=np.int32).reshape(-1))
     return arr, len(arr) // 2
+
+
+def coded_qr_ws_panel_fallbacks(plan: int, ws, stream=None) -> int:
+    """Blocking: panel leaves orthogonalised by the column-wise fallback."""
+    v = ctypes.c_int32(0)
+    _check(LIB.coded_qr_ws_panel_fallbacks(ctypes.c_void_p(plan), _ptr(ws), ctypes.c_void_p(_stream(stream)),
+                                           ctypes.byref(v)), "coded_qr_ws_panel_fallbacks")
+    return v.value
 
 
 def coded_qr_erase(plan: int, Q, R, nodes, stream=None) -> int:
@@ -366,6 +391,11 @@ class CodedQR:
         if st not in (CQR_OK, CQR_EBREAKDOWN):
             _check(st, "coded_qr_ws_info")
         return info
+
+    def panel_fallbacks(self) -> int:
+        """Panel leaves the last factorization handed to the column-wise CGS2
+        fallback after a Cholesky-QR breakdown (blocking)."""
+        return coded_qr_ws_panel_fallbacks(self.plan, self.ws)
 
     def erase(self, At, R, nodes):
         _check(coded_qr_erase(self.plan, At, R, nodes), "coded_qr_erase")

@@ -36,6 +36,8 @@ struct cqr_plan_s {
   int64_t ldx = 0, xstride = 0;   // first-pass panel copies for the early update (0: none)
   size_t off_part = 0, off_part2 = 0, off_S = 0, off_G = 0, off_T = 0, off_R1 = 0, off_X = 0, off_T2 = 0,
          ws_bytes = 0;
+  int ninfo = 0;           // ints of the info area: 64 status words, then one fallback flag per panel
+  double eta = 0.0;        // ICGS threshold in use
   // lookahead: the panel chain's stream, the update stream and four events,
   // created on first use on the device current at that time
   hipStream_t chain = nullptr, side = nullptr;
@@ -49,7 +51,7 @@ struct cqr_plan_s {
 };
 
 enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_CHOL, PH_APPLY, PH_INPANEL, PH_TRAIL_TN,
-             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_REENCODE, PH_SOLVE,
+             PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_COLPANEL, PH_SOLVE,
              PH_ADJOINT };
 static_assert(PH_ADJOINT + 1 == CQR_NPHASES, "phase list and header disagree");
 
@@ -208,6 +210,7 @@ cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws, bool second = false) {
   char* b = static_cast<char*>(ws);
   cqr::Scratch s;
   s.info = reinterpret_cast<int*>(b);
+  s.fb = s.info + 64;
   s.part = reinterpret_cast<double*>(b + (second ? p.off_part2 : p.off_part));
   s.npart = p.npart;
   s.S = reinterpret_cast<double*>(b + p.off_S);
@@ -349,9 +352,9 @@ void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B,
 }
 
 void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64_t lda, const double* B,
-        int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st, bool f32 = false) {
+        int64_t ldb, int64_t M, int N, int K, const cqr::Scratch& s, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return;
-  cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, f32);
+  cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s);
   a.prio = chain_phase(phase);
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)M * K + (double)K * N);
   const double upd = 16.0 * (double)M * N;
@@ -365,11 +368,32 @@ void nn(cqr_plan_s& p, int phase, double* C, int64_t ldc, const double* A, int64
   }
 }
 
+// The second pass (pass 2) gets the panel P (for its column-wise breakdown
+// fallback) and, when an update already started from the panel's first
+// pass, that panel's fallback flag.
 void chol(cqr_plan_s& p, const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-          int64_t ldx, double* Rbar, int panel, const cqr::Scratch& s, hipStream_t st, double* Tcopy = nullptr) {
+          int64_t ldx, double* Rbar, int panel, const cqr::Scratch& s, hipStream_t st, double* Tcopy = nullptr,
+          double* P = nullptr, int64_t ldp = 0, int* fb = nullptr) {
   prof(p, PH_CHOL, 2.0 * w * w * w * (X ? 2.0 : 1.0),
        8.0 * w * w * (pass == 1 ? 3.0 : (X ? 6.0 : 4.0) + (Tcopy ? 1.0 : 0.0)), st,
-       [&] { cqr::launch_chol(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s, st, Tcopy); });
+       [&] { cqr::launch_chol(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s, st, Tcopy, P, ldp, p.mp, fb); });
+}
+
+// Column-wise panel modes (CGS2, ICGS, MGS): one workgroup orthogonalises the
+// leaf P (m' x w) and stores R[leaf, leaf].  Flops: 4 m' w^2 for CGS2 (two
+// projections, each a product and an update), 2 m' w^2 for MGS; bytes: the
+// panel read and written once (the minimum).
+void colpanel(cqr_plan_s& p, double* P, int64_t ldq, int w, double* Rout, int64_t ldr, int panel,
+              const cqr::Scratch& s, hipStream_t st) {
+  cqr::ColArgs a{};
+  a.P = P; a.ldp = ldq; a.mrows = p.mp; a.w = w;
+  a.mode = p.cfg.panel == CQR_PANEL_MGS ? cqr::COLWISE_MGS
+                                         : (p.cfg.panel == CQR_PANEL_ICGS ? cqr::COLWISE_ICGS : cqr::COLWISE_CGS2);
+  a.eta = p.eta;
+  a.Rout = Rout; a.ldr = ldr; a.info = s.info; a.panel = panel;
+  const double mult = a.mode == cqr::COLWISE_MGS ? 2.0 : 4.0;
+  prof(p, PH_COLPANEL, mult * (double)p.mp * w * w, 16.0 * (double)p.mp * w, st,
+       [&] { cqr::launch_colpanel(a, st); });
 }
 
 // The product W = X^T B of an update that starts before its panel is
@@ -395,11 +419,13 @@ cqr::TnArgs tn_early(cqr_plan_s& p, const double* X, int64_t ldx, const double* 
 
 // out = T^T W for the W that tn_early left (T: w x w, the second pass's
 // R^{-1}): the update's coefficients against the finished panel.
+// (fb, P, ldp: the panel's fallback flag and the finished panel, from which
+// the coefficients are formed directly if its second pass fell back.)
 void tn_tmul(cqr_plan_s& p, const cqr::TnArgs& a, const double* T, int w, double* out, int64_t ldo,
-             hipStream_t st) {
+             hipStream_t st, const int* fb, const double* P, int64_t ldp) {
   const double in = a.nsplit > 1 ? partial_bytes(a.nsplit, a.ntiles) : 8.0 * (double)w * a.N;
   prof(p, PH_REDUCE, (a.nsplit - 1.0) * w * a.N + 2.0 * w * w * (double)a.N, in + 8.0 * (w * w + (double)w * a.N),
-       st, [&] { cqr::launch_tn_reduce_tmul(a, T, w, out, ldo, st); });
+       st, [&] { cqr::launch_tn_reduce_tmul(a, T, w, out, ldo, st, fb, P, ldp); });
 }
 
 // The split re-projection update C -= A B with the panel's first Cholesky
@@ -412,7 +438,7 @@ bool nn_chol(cqr_plan_s& p, double* C, int64_t ldc, const double* A, int64_t lda
              int64_t M, int N, int K, const cqr::CholArgs& c, const cqr::Scratch& s, hipStream_t st,
              double* X = nullptr, int64_t ldx = 0) {
   if (M <= 0 || N <= 0 || K <= cqr::kLeaf || c.w > cqr::kLeaf) return false;
-  cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s, false);
+  cqr::NnArgs a = cqr::nn_setup(C, ldc, A, lda, B, ldb, M, N, K, s);
   a.prio = 1;
   if (a.nsplit <= 1 || a.tilesN != 1 || N != c.w) return false;
   const double fl = 2.0 * M * N * (double)K + 2.0 * c.w * c.w * c.w;
@@ -433,7 +459,7 @@ bool nn_chol(cqr_plan_s& p, double* C, int64_t ldc, const double* A, int64_t lda
 bool apply_update(cqr_plan_s& p, double* C, int64_t ldc, double* P, int64_t ldq, const double* B, int64_t ldb,
                   int w, const cqr::Scratch& s, hipStream_t st) {
   const int64_t mp = p.mp;
-  const cqr::NnArgs a = cqr::nn_setup(C, ldc, P, ldq, B, ldb, mp, w, w, s, false);
+  const cqr::NnArgs a = cqr::nn_setup(C, ldc, P, ldq, B, ldb, mp, w, w, s);
   if (a.tilesN != 1 || a.K != w || w > cqr::kLeaf) return false;
   bool launched = false;
   prof(p, PH_APPLY, 4.0 * mp * w * w, 8.0 * (4.0 * mp * w + 2.0 * w * w), st,
@@ -451,18 +477,23 @@ void apply(cqr_plan_s& p, double* P, int64_t ldq, int w, const cqr::Scratch& s, 
 void cholqr_pass(cqr_plan_s& p, double* P, int64_t ldq, int w, int pass, double* Rout, int64_t ldr, int panel,
                  const cqr::Scratch& s, hipStream_t st) {
   tn(p, PH_GRAM, P, ldq, P, ldq, w, w, p.mp, s.G, w, nullptr, 0, s, st);
-  chol(p, s.G, w, w, pass, Rout, ldr, nullptr, 0, nullptr, panel, s, st);
+  chol(p, s.G, w, w, pass, Rout, ldr, nullptr, 0, nullptr, panel, s, st, nullptr, P, ldq);
   apply(p, P, ldq, w, s, st);
 }
 
 // Panel of w columns starting at column c: leaves of <= kLeaf columns are
-// orthogonalised by two Cholesky-QR passes; wider panels are split, the right
-// part projected (twice) against the left part before being factored.
+// orthogonalised by two Cholesky-QR passes (or column by column in the CGS2,
+// ICGS and MGS panel modes); wider panels are split, the right part projected
+// (twice) against the left part before being factored.
 void factor_panel(cqr_plan_s& p, double* Q, int64_t ldq, double* R, int64_t ldr, int64_t c, int w,
                   int panel, const cqr::Scratch& s, hipStream_t st) {
   const int64_t mp = p.mp;
   if (w <= kLeaf) {
     double* P = Q + c * ldq;
+    if (p.cfg.panel != CQR_PANEL_CHOLQR2) {
+      colpanel(p, P, ldq, w, R + c + c * ldr, ldr, panel, s, st);
+      return;
+    }
     cholqr_pass(p, P, ldq, w, 1, nullptr, 0, panel, s, st);
     cholqr_pass(p, P, ldq, w, 2, R + c + c * ldr, ldr, panel, s, st);
     return;
@@ -492,7 +523,7 @@ const char* coded_qr_status_string(cqr_status s) {
     case CQR_ESINGULAR: return "singular generator submatrix";
     case CQR_EHIP: return "HIP runtime error";
     case CQR_ENOMEM: return "out of memory / workspace too small";
-    case CQR_EBREAKDOWN: return "panel breakdown (Gram matrix not positive definite)";
+    case CQR_EBREAKDOWN: return "panel breakdown: a panel column is zero after projection (rank-deficient input)";
   }
   return "unknown status";
 }
@@ -511,6 +542,8 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   if (c.kh > c.pc && c.storage == CQR_IN_NODE) return CQR_EINVAL;
   if (c.storage != CQR_OUT_OF_NODE && c.storage != CQR_IN_NODE) return CQR_EINVAL;
   if (c.precision != CQR_FP64 && c.precision != CQR_TRAIL_FP32) return CQR_EINVAL;
+  if (c.panel < CQR_PANEL_CHOLQR2 || c.panel > CQR_PANEL_MGS) return CQR_EINVAL;
+  if (!(c.icgs_eta >= 0.0 && c.icgs_eta <= 1.0)) return CQR_EINVAL;   // also rejects NaN
   if (c.lookahead != 0 && c.lookahead != 1) return CQR_EINVAL;
   if (c.kv > 0 && !v_tilde) return CQR_EINVAL;
   if (c.kh > 0 && !gh) return CQR_EINVAL;
@@ -519,6 +552,7 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   cqr_plan_s* p = new (std::nothrow) cqr_plan_s();
   if (!p) return CQR_ENOMEM;
   p->cfg = c;
+  p->eta = c.icgs_eta > 0.0 ? c.icgs_eta : 1.0 / std::sqrt(2.0);
   p->bs = c.m / c.pr;
   p->bw = c.n / c.pc;
   p->hr = c.n / c.pr;
@@ -557,7 +591,8 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   // workgroups (32 KB per partial tile)
   p->npart = std::max<int64_t>(1024, 4 * maxTiles);
   p->nS = std::max<int64_t>(n * b, (int64_t)kLeaf * kLeaf);   // S with the fused Gram rows: c1 x b, c1 <= n
-  size_t off = 256;
+  p->ninfo = 64 + (int)(n / b);
+  size_t off = align256(sizeof(int) * (size_t)p->ninfo);
   p->off_part = off;  off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
   p->off_part2 = off; off = align256(off + sizeof(double) * (size_t)p->npart * kTile * kTile);
   p->off_S = off;    off = align256(off + sizeof(double) * (size_t)p->nS);
@@ -627,6 +662,16 @@ cqr_status coded_qr_plan_generators(cqr_plan p, double* gv, double* gh) {
 
 int32_t coded_qr_plan_ftol(cqr_plan p) { return p ? p->ftol : -1; }
 
+cqr_status coded_qr_plan_placement(cqr_plan p, int32_t* qrow, int32_t* rcol) {
+  if (!p) return CQR_EINVAL;
+  const bool in = p->cfg.storage == CQR_IN_NODE;
+  if (qrow)
+    for (int k = 0; k < p->cfg.kv; ++k) qrow[k] = in ? k % p->cfg.pr : p->cfg.pr + k;
+  if (rcol)
+    for (int k = 0; k < p->cfg.kh; ++k) rcol[k] = in ? k % p->cfg.pc : p->cfg.pc + k;
+  return CQR_OK;
+}
+
 int64_t coded_qr_plan_r_rows(cqr_plan p) { return p ? p->rrows : 0; }
 
 size_t coded_qr_workspace_bytes(cqr_plan p) { return p ? p->ws_bytes : 0; }
@@ -639,19 +684,18 @@ cqr_status coded_qr_encode(cqr_plan p, double* At, int64_t ldat, hipStream_t st)
   a.At = At; a.ld = ldat;
   a.m = p->cfg.m; a.n = p->cfg.n; a.bs = p->bs; a.bw = p->bw;
   a.pr = p->cfg.pr; a.pc = p->cfg.pc; a.kv = p->cfg.kv; a.kh = p->cfg.kh;
-  if (a.kv > 0) {
-    for (size_t e = 0; e < p->gv.size(); ++e) a.g[e] = p->gv[e];
-    const double c = (double)a.kv * a.bs;
-    prof(*p, PH_ENCODE, 2.0 * a.kv * a.pr * a.bs * a.n, 8.0 * (a.m + c) * a.n, st,
-         [&] { cqr::launch_encode_rows(a, st); });
-  }
-  if (a.kh > 0) {
-    for (int k = 0; k < a.kh; ++k)
-      for (int t = 0; t < a.pc; ++t) a.g[k * a.pc + t] = p->gh[t * a.kh + k];
-    const double mpd = (double)p->mp;
-    prof(*p, PH_ENCODE, 2.0 * a.kh * a.pc * mpd * a.bw, 8.0 * mpd * (a.n + (double)a.kh * a.bw), st,
-         [&] { cqr::launch_encode_cols(a, st); });
-  }
+  for (size_t e = 0; e < p->gv.size(); ++e) a.g[e] = p->gv[e];
+  for (int l = 0; l < a.kh; ++l)
+    for (int t = 0; t < a.pc; ++t) a.gc[l * cqr::kMaxGrid + t] = p->gh[t * a.kh + l];
+  // one pass: A read once, every checksum element written once (without a
+  // column code, e.g. a p_r x 1 grid, the checksum rows alone)
+  const double m = (double)a.m, n = (double)a.n, c = (double)a.kv * a.bs, d = (double)a.kh * a.bw;
+  prof(*p, PH_ENCODE, 2.0 * (c * a.pr * n + (m + c) * a.pc * d), 8.0 * (m * n + c * n + m * d + c * d), st, [&] {
+    if (a.kh > 0)
+      cqr::launch_encode_fused(a, st);
+    else
+      cqr::launch_encode_rows(a, st);
+  });
   return hip_status();
 }
 
@@ -666,7 +710,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
   cqr::Scratch s = scratch_of(*p, ws);
   const cqr::Scratch s2 = scratch_of(*p, ws, true);
   if (pb == 0) {
-    prof(*p, PH_OTHER, 0.0, 256.0, st, [&] { cqr::launch_zero_ints(s.info, 64, st); });
+    prof(*p, PH_OTHER, 0.0, 4.0 * p->ninfo, st, [&] { cqr::launch_zero_ints(s.info, p->ninfo, st); });
     prof(*p, PH_OTHER, 0.0, 8.0 * n * N, st, [&] { cqr::launch_fill_zero(R, ldr, n, N, st); });
   }
   const bool la = p->cfg.lookahead && pe - pb > 1 && side_ready(*p);
@@ -680,31 +724,27 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     if (e != hipSuccess) return hip_fail(e);
     st = p->chain;
   }
-  // the trailing-update products in FP32 (mixed precision) or FP64
+  // Mixed precision: the coefficient products R_bar = Qbar^T Q_t of the
+  // trailing update (and of the early update) run on FP32 MFMA.  Every column
+  // operation on the encoded matrix -- the rank-b update Q_t -= Qbar R_bar, the
+  // re-projection, the panel transforms -- stays FP64: a column operation
+  // applied with the same coefficients to every row keeps Q_2 = G_v Q_1 to
+  // FP64 rounding whatever the coefficients are, and R records exactly the
+  // coefficients applied, so A~ = Q~ R holds to FP64 rounding as well.  The
+  // FP32 error of R_bar leaves components of Qbar in the trailing columns;
+  // the next panels' FP64 re-projection removes them and adds their
+  // coefficients into R.
   const bool f32 = p->cfg.precision == CQR_TRAIL_FP32;
-  // With FP32 updates the systematic and checksum rows of a column are
-  // rounded independently, so Q_2 = G_v Q_1 drifts by the FP32 rounding of
-  // every update.  Relative to a column's final norm that drift grows like
-  // u32 kappa(A), and decoding would carry it into recovered blocks.  Each
-  // panel's checksum rows are therefore re-derived from its systematic rows in
-  // FP64 just before the panel is factored; the panel factorization is a
-  // column operation, so finished columns keep the relation to FP64 rounding.
-  cqr::EncodeArgs renc{};
-  const bool reencode = f32 && p->cfg.kv > 0;
-  if (reencode) {
-    renc.ld = ldq;
-    renc.m = p->cfg.m; renc.n = b; renc.bs = p->bs; renc.bw = p->bw;
-    renc.pr = p->cfg.pr; renc.pc = p->cfg.pc; renc.kv = p->cfg.kv; renc.kh = 0;
-    for (size_t e = 0; e < p->gv.size(); ++e) renc.g[e] = p->gv[e];
-  }
   // Panel k's update of columns [from, to):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
   auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
     double* Rb = R + c0 + from * ldr;
     const double* P = Q + c0 * ldq;
     tn(*p, PH_TRAIL_TN, P, ldq, Q + from * ldq, ldq, (int)b, (int)(to - from), mp, Rb, ldr, nullptr, 0, sc, ss, -1,
        f32);
-    nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss, f32);
+    nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss);
   };
+  bool deferred = false;       // a wide panel's update of the columns after the next panel, not yet forked
+  int64_t def_c0 = 0, def_from = 0;
   bool side_pending = false;   // ev_side marks side-stream work the chain has not waited for
   bool side_tail = false;      // side-stream work queued after the last ev_side record
   // the chain waits for the side stream's update of the next panel's columns
@@ -739,13 +779,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     const int64_t c0 = (int64_t)k * b, c1 = c0 + b;
     double* P = Q + c0 * ldq;
     const bool next = la && k + 1 < pe;     // panel k+1 is factored in this call
-    if (reencode) {
-      renc.At = P;
-      const double c = (double)renc.kv * renc.bs;
-      prof(*p, PH_REENCODE, 2.0 * c * renc.pr * b, 8.0 * (renc.m + c) * b, st,
-           [&] { cqr::launch_encode_rows(renc, st); });
-    }
-    if (b <= kLeaf) {
+    if (b <= kLeaf && p->cfg.panel == CQR_PANEL_CHOLQR2) {
       // First Cholesky-QR pass.  With re-projection its Gram matrix comes from
       // the same product as the coefficients, [Q[:, :c0] | P]^T P: since the
       // re-projection coefficients S are at rounding level, P^T P equals the
@@ -799,15 +833,15 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       }
       tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, next ? 2 * (int)b : (int)b, mp, s.G, b, nullptr, 0, s, st);
       chol(*p, s.G, b, (int)b, 2, R + c0 + c0 * ldr, ldr, next ? s.G + b * b : nullptr, b,
-           next ? R + c0 + c1 * ldr : nullptr, k, s, st, early ? s.T2 : nullptr);
+           next ? R + c0 + c1 * ldr : nullptr, k, s, st, early ? s.T2 : nullptr, P, ldq, early ? s.fb + k : nullptr);
       // P <- P1 R2^{-1}, and with lookahead Q_next -= P R[panel, next] (one
-      // launch in FP64; the FP32 form keeps its FP32 update)
-      const bool fused = next && !f32 &&
+      // launch)
+      const bool fused = next &&
                          apply_update(*p, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, (int)b, s, st);
       if (!fused) apply(*p, P, ldq, (int)b, s, st);
       if (next) {
         if (!fused)
-          nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st, f32);
+          nn(*p, PH_TRAIL_NN, Q + c1 * ldq, ldq, P, ldq, R + c0 + c1 * ldr, ldr, mp, (int)b, (int)b, s, st);
         if (early) {
           // the early update's reduction and rank-b update, after the panel
           hipError_t e = hipEventRecord(p->ev_apply, st);
@@ -818,15 +852,15 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
           // columns after them are updated while the chain moves on (the
           // chain touches them only after join_side_all).
           double* Rb = R + c0 + (c1 + b) * ldr;
-          tn_tmul(*p, ea, s.T2, (int)b, Rb, ldr, p->side);
+          tn_tmul(*p, ea, s.T2, (int)b, Rb, ldr, p->side, s.fb + k, P, ldq);
           const int64_t near = std::min<int64_t>(b, N - c1 - b);
-          nn(*p, PH_TRAIL_NN, Q + (c1 + b) * ldq, ldq, P, ldq, Rb, ldr, mp, (int)near, (int)b, s2, p->side, f32);
+          nn(*p, PH_TRAIL_NN, Q + (c1 + b) * ldq, ldq, P, ldq, Rb, ldr, mp, (int)near, (int)b, s2, p->side);
           e = hipEventRecord(p->ev_side, p->side);
           if (e != hipSuccess) return hip_fail(e);
           side_pending = true;
           if (c1 + b + near < N) {
             nn(*p, PH_TRAIL_NN, Q + (c1 + b + near) * ldq, ldq, P, ldq, Rb + near * ldr, ldr, mp,
-               (int)(N - c1 - b - near), (int)b, s2, p->side, f32);
+               (int)(N - c1 - b - near), (int)b, s2, p->side);
             side_tail = true;
           }
         } else if (c1 + b < N) {
@@ -839,22 +873,35 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       }
       continue;
     }
-    // Panels wider than a Cholesky-QR leaf: re-projection, recursive panel,
-    // then the update (the next panel's columns first with lookahead).
+    // Panels wider than a Cholesky-QR leaf, and every panel of the
+    // column-wise modes: re-projection, recursive panel, then the update (the
+    // next panel's columns first with lookahead).
     if (p->cfg.reproject && k > 0) {
       tn(*p, PH_REPROJ_TN, Q, ldq, P, ldq, (int)c0, (int)b, mp, s.S, c0, R + c0 * ldr, ldr, s, st);
       nn(*p, PH_REPROJ_NN, P, ldq, Q, ldq, s.S, c0, mp, (int)b, (int)c0, s, st);
+    }
+    // With lookahead the previous panel's update of the columns after this
+    // panel starts only here, behind this panel's re-projection: the two
+    // large products run one after the other instead of sharing the GPU, and
+    // the update overlaps this panel's factorization, whose kernels are small.
+    if (deferred) {
+      if (hipError_t e = fork_side(def_c0, def_from); e != hipSuccess) return hip_fail(e);
+      deferred = false;
     }
     factor_panel(*p, Q, ldq, R, ldr, c0, (int)b, k, s, st);
     if (c1 >= N) continue;
     if (hipError_t e = join_side_all(); e != hipSuccess) return hip_fail(e);
     if (next && c1 + b < N) {
       trail(c0, c1, c1 + b, s, st);
-      if (hipError_t e = fork_side(c0, c1 + b); e != hipSuccess) return hip_fail(e);
+      deferred = true;
+      def_c0 = c0;
+      def_from = c1 + b;
     } else {
       trail(c0, c1, N, s, st);
     }
   }
+  if (deferred)
+    if (hipError_t e = fork_side(def_c0, def_from); e != hipSuccess) return hip_fail(e);
   if (hipError_t e = join_side_all(); e != hipSuccess) return hip_fail(e);
   if (la) {
     // the caller's stream waits for the chain (which has joined the updates)
@@ -887,6 +934,17 @@ cqr_status coded_qr_ws_info(cqr_plan p, const void* ws, hipStream_t st, int32_t*
   if (he != hipSuccess) return hip_fail(he);
   *info = v;
   return v ? CQR_EBREAKDOWN : CQR_OK;
+}
+
+cqr_status coded_qr_ws_panel_fallbacks(cqr_plan p, const void* ws, hipStream_t st, int32_t* count) {
+  if (!p || !ws || !count) return CQR_EINVAL;
+  hipError_t he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
+  int32_t v = 0;
+  he = hipMemcpy(&v, static_cast<const int32_t*>(ws) + 2, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return hip_fail(he);
+  *count = v;
+  return CQR_OK;
 }
 
 cqr_status coded_qr_erase(cqr_plan p, double* Q, int64_t ldq, double* R, int64_t ldr, const int32_t* ij,

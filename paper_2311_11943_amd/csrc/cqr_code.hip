@@ -5,6 +5,7 @@
 // covers whole 128-byte lines.
 #include "cqr_kernels.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace cqr {
@@ -17,8 +18,9 @@ static unsigned grid_for(int64_t n) {
 }
 
 // --------------------------------------------------------------------------
-// Encode, column pass: checksum rows  C_(k,J) = sum_t g~_v[k][t] A_(t,J)
-// for all n systematic columns.  Thread = (row r in a block, column c).
+// Checksum rows alone, C_(k,J) = sum_t g~_v[k][t] A_(t,J) for all n columns
+// (R's vertical code when the plan has no horizontal code).  Thread = (row r
+// in a block, column c).
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void encode_rows_kernel(EncodeArgs a) {
   int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -39,34 +41,91 @@ __global__ __launch_bounds__(kThreads) void encode_rows_kernel(EncodeArgs a) {
     if (k < a.kv) col[a.m + k * a.bs + r] = acc[k];
 }
 
-// Encode, row pass: checksum columns  C_(I,k) = sum_t g~_h[t][k] A~_(I,t) for
-// every row of A~ (systematic and checksum rows; the corner follows).
-__global__ __launch_bounds__(kThreads) void encode_cols_kernel(EncodeArgs a) {
-  const int64_t mp = a.m + a.kv * a.bs;
-  int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= mp * a.bw) return;
-  int64_t row = e % mp, s = e / mp;
-  double acc[kMaxGen];
+// --------------------------------------------------------------------------
+// Encode in one pass (the whole encoding equation): checksum rows, checksum
+// columns and corner from a single read of A.  A workgroup takes R = 256 / T
+// consecutive rows r of a block row at one column position s of a block
+// column, and walks the p_r block rows u; thread (rho, t) loads the element
+// at row u bs + r, column t bw + s for every u up front (all its loads in
+// flight at once), and
+//   - as a row-code thread (t < p_c) sums C_k += g~_v[k][u] A_(u,t)[r, s]
+//     over u (checksum block row k, block column t);
+//   - as a column-code thread (t = l < K_h) forms, for each u, the checksum
+//     column entry sum_t' g~_h[t'][l] A_(u,t')[r, s] from the workgroup's
+//     LDS copy of that row of blocks, and after the walk the corner entries
+//     sum_t' g~_h[t'][l] C_k(t') from the row-code threads' sums.
+// Threads (rho, t) with the same t read R consecutive rows of one column:
+// whole cache-line segments per wave and column.  Every element of A is read
+// once and every checksum element written once: 8 (mn + cn + md + cd) bytes.
+// --------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(kThreads) void encode_fused_kernel(EncodeArgs a) {
+  constexpr int R = kThreads / T;
+  __shared__ double X[2][T][R + 1];
+  __shared__ double Cl[kMaxGen][T][R + 1];
+  __shared__ double Gc[kMaxGen][kMaxGrid];
+  const int tid = threadIdx.x, rho = tid % R, t = tid / R;
+  const int64_t nseg = (a.bs + R - 1) / R;
+  const int64_t s = blockIdx.x / nseg;
+  const int64_t r = (blockIdx.x % nseg) * R + rho;
+  const bool rok = r < a.bs;
+  const bool rowt = t < a.pc, colt = t < a.kh;
+  for (int e = tid; e < kMaxGen * kMaxGrid; e += kThreads) Gc[e / kMaxGrid][e % kMaxGrid] = a.gc[e];
+  double x[kMaxGrid];
+  const double* src = a.At + r + (t * a.bw + s) * a.ld;
 #pragma unroll
-  for (int k = 0; k < kMaxGen; ++k) acc[k] = 0.0;
-  for (int t = 0; t < a.pc; ++t) {
-    double v = a.At[row + (t * a.bw + s) * a.ld];
+  for (int u = 0; u < kMaxGrid; ++u) x[u] = (u < a.pr && rok && rowt) ? src[u * a.bs] : 0.0;
+  double c[kMaxGen];
+#pragma unroll
+  for (int k = 0; k < kMaxGen; ++k) c[k] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kMaxGrid; ++u) {
+    if (u >= a.pr) break;
+    X[u & 1][t][rho] = x[u];
 #pragma unroll
     for (int k = 0; k < kMaxGen; ++k)
-      if (k < a.kh) acc[k] += a.g[k * a.pc + t] * v;
+      if (k < a.kv) c[k] += a.g[k * a.pr + u] * x[u];
+    __syncthreads();
+    if (colt && rok) {
+      double d = 0.0;
+      for (int tt = 0; tt < a.pc; ++tt) d += Gc[t][tt] * X[u & 1][tt][rho];
+      a.At[u * a.bs + r + (a.n + t * a.bw + s) * a.ld] = d;
+    }
   }
+  if (a.kv == 0) return;
+  if (rowt) {
 #pragma unroll
-  for (int k = 0; k < kMaxGen; ++k)
-    if (k < a.kh) a.At[row + (a.n + k * a.bw + s) * a.ld] = acc[k];
+    for (int k = 0; k < kMaxGen; ++k)
+      if (k < a.kv) {
+        Cl[k][t][rho] = c[k];
+        if (rok) a.At[a.m + k * a.bs + r + (t * a.bw + s) * a.ld] = c[k];
+      }
+  }
+  __syncthreads();
+  if (colt && rok) {
+    for (int k = 0; k < a.kv; ++k) {
+      double e = 0.0;
+      for (int tt = 0; tt < a.pc; ++tt) e += Gc[t][tt] * Cl[k][tt][rho];
+      a.At[a.m + k * a.bs + r + (a.n + t * a.bw + s) * a.ld] = e;
+    }
+  }
+}
+
+void launch_encode_fused(const EncodeArgs& a, hipStream_t st) {
+  const int T = std::max(a.pc, a.kh) <= 8 ? 8 : (std::max(a.pc, a.kh) <= 16 ? 16 : 32);
+  const int R = kThreads / T;
+  const unsigned grid = (unsigned)(((a.bs + R - 1) / R) * a.bw);
+  if (T == 8)
+    hipLaunchKernelGGL(encode_fused_kernel<8>, dim3(grid), dim3(kThreads), 0, st, a);
+  else if (T == 16)
+    hipLaunchKernelGGL(encode_fused_kernel<16>, dim3(grid), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(encode_fused_kernel<32>, dim3(grid), dim3(kThreads), 0, st, a);
 }
 
 void launch_encode_rows(const EncodeArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(encode_rows_kernel, dim3(grid_for(a.bs * a.n)), dim3(kThreads), 0, st, a);
-}
-
-void launch_encode_cols(const EncodeArgs& a, hipStream_t st) {
-  int64_t mp = a.m + a.kv * a.bs;
-  hipLaunchKernelGGL(encode_cols_kernel, dim3(grid_for(mp * a.bw)), dim3(kThreads), 0, st, a);
 }
 
 // --------------------------------------------------------------------------

@@ -15,6 +15,7 @@
 // Reductions over long K are split across blocks; partial tiles go to the
 // workspace and a second small kernel sums them in split order, so results do
 // not depend on scheduling and no device-wide fence is needed.
+#include "cqr_colwise.hpp"
 #include "cqr_kernels.hpp"
 
 #include <algorithm>
@@ -31,10 +32,28 @@ __device__ __forceinline__ v4d mfma(double x, double y, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
 }
 
-// FP32 product of FP64 operands rounded to FP32, FP32 accumulation (the
-// mixed-precision trailing update).  Operand lanes as in the FP64 form.
+// FP32 product of FP64 operands rounded to FP32 (the mixed-precision
+// coefficient product R_bar = Qbar^T Q_t).  Operand lanes as in the FP64 form.
+// The product kernels accumulate it in FP32 over 16 k-values only (four MFMA
+// steps) and add each group's sums into FP64 accumulators, so the rounding of
+// the reduction does not grow with K.
 __device__ __forceinline__ v4f mfma(double x, double y, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32((float)x, (float)y, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v4f mfma(float x, float y, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+}
+
+// Operand type of the product kernels' MFMA steps.
+template <bool F32> struct OpT { typedef double type; };
+template <> struct OpT<true> { typedef float type; };
+
+// acc += t, element by element in FP64 (one slab's FP32 sums into the FP64
+// accumulators of the mixed-precision product).
+__device__ __forceinline__ void widen_add(v4d& acc, const v4f& t) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] += (double)t[r];
 }
 
 // Result layout of the transposed-issue 16x16x4 products: lane (li, g),
@@ -43,8 +62,6 @@ __device__ __forceinline__ v4f mfma(double x, double y, v4f c) {
 // consecutive columns 4g .. 4g+3.
 __device__ __forceinline__ int colsub(int r, int g, bool f32) { return f32 ? 4 * g + r : 4 * r + g; }
 
-template <bool F32> struct AccT { typedef v4d type; };
-template <> struct AccT<true> { typedef v4f type; };
 
 // Partial-tile layout shared by the product and reduction kernels: tile
 // `tile` of split `sp`, wave w, accumulator element q (16 per lane), lane l at
@@ -118,7 +135,7 @@ __device__ __forceinline__ void store_quadrant(double* C, int64_t ldc, double* C
 
 template <class Acc>
 __device__ __forceinline__ void tn_store(const TnArgs& a, const Acc (&acc)[2][2], int tile, int split, int wave,
-                                         int lane, int i0, int j0) {
+                                         int lane, int i0, int j0, bool f32_layout) {
   const int li = lane & 15, g = lane >> 4;
   if (a.nsplit > 1) {
     double* mine = a.part + part_off(split, a.ntiles, tile, wave);
@@ -133,13 +150,14 @@ __device__ __forceinline__ void tn_store(const TnArgs& a, const Acc (&acc)[2][2]
   double v[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = acc[e >> 3][(e >> 2) & 1][e & 3];
-  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.M2, a.N, i0, j0, li, g, sizeof(acc[0][0][0]) == 4, v);
+  store_quadrant(a.C, a.ldc, a.C2, a.ldc2, a.M, a.M2, a.N, i0, j0, li, g, f32_layout, v);
 }
 
 template <int TAG, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void tn_lds_kernel(TnArgs a) {
   if (a.prio) __builtin_amdgcn_s_setprio(2);
-  typedef typename AccT<F32>::type Acc;
+  typedef v4d Acc;    // FP64 accumulators (FP32 products are widened per slab)
+  typedef typename OpT<F32>::type Op;
   __shared__ double sA[2][64 * LDP];
   __shared__ double sB[2][64 * LDP];
   const int tile = blockIdx.x, split = blockIdx.y;
@@ -169,7 +187,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 16) {
-      double xa[2][4], xb[2][4];
+      [[maybe_unused]] v4f t32[2][2];
+      if constexpr (F32)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) t32[x][y] = v4f{0, 0, 0, 0};
+      Op xa[2][4], xb[2][4];   // FP32 operands are rounded as they leave LDS
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const double* pa = &sA[buf][(ia0 + 16 * t + li) * LDP + kk + 4 * g];
@@ -184,7 +208,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+          for (int y = 0; y < 2; ++y) {
+            if constexpr (F32)
+              t32[x][y] = mfma(xb[y][s], xa[x][s], t32[x][y]);
+            else
+              acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+          }
+      if constexpr (F32)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) widen_add(acc[x][y], t32[x][y]);
     }
   };
   // slab sl's first k (clamped to the last full slab: prefetches past the end
@@ -259,7 +293,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     __syncthreads();
     compute(buf);
   }
-  tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0);
+  tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0, F32);
 }
 
 // The same product with 16-deep slabs (36 KB of LDS, three waves per SIMD),
@@ -278,7 +312,8 @@ template <int TAG, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void tn16_kernel(TnArgs a) {
   constexpr int SK = 16, LW = SK + 2, NQ = 2, TPC = SK / 2, CPP = 256 / TPC;
   if (a.prio) __builtin_amdgcn_s_setprio(2);
-  typedef typename AccT<F32>::type Acc;
+  typedef v4d Acc;    // FP64 accumulators (FP32 products are widened per slab)
+  typedef typename OpT<F32>::type Op;
   __shared__ double sA[2][64 * LW];
   __shared__ double sB[2][64 * LW];
   const int tile = blockIdx.x, split = blockIdx.y;
@@ -304,7 +339,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   const int ia0 = (wave & 1) * 32, jb0 = (wave >> 1) * 32;
   const int nfull = (int)((ke - kb) / SK);
   auto compute = [&](int buf) {
-    double xa[2][4], xb[2][4];
+    Op xa[2][4], xb[2][4];   // FP32 operands are rounded as they leave LDS
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const double* pa = &sA[buf][(ia0 + 16 * t + li) * LW + 4 * g];
@@ -314,12 +349,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
       xb[t][0] = b0.x; xb[t][1] = b0.y; xb[t][2] = b1.x; xb[t][3] = b1.y;
     }
+    [[maybe_unused]] v4f t32[2][2];
+    if constexpr (F32)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) t32[x][y] = v4f{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+        for (int y = 0; y < 2; ++y) {
+          if constexpr (F32)
+            t32[x][y] = mfma(xb[y][s], xa[x][s], t32[x][y]);
+          else
+            acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+        }
+    if constexpr (F32)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) widen_add(acc[x][y], t32[x][y]);
   };
   auto koff = [&](int sl) { return kb + (int64_t)std::min(sl, nfull - 1) * SK; };
   v2d ra0[NQ], rb0[NQ], ra1[NQ], rb1[NQ];
@@ -379,7 +430,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     __syncthreads();
     compute(buf);
   }
-  tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0);
+  tn_store(a, acc, tile, split, wave, lane, tm * 64 + ia0, tn * 64 + jb0, F32);
 }
 
 // Two tile rows per workgroup (512 threads): waves 0-3 compute tile row
@@ -396,10 +447,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // 128 x 20480 product with depth 24576 at 55 against 52 (each with the split
 // count that fills its grid).
 template <int TAG, bool F32>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) void tn2_kernel(TnArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void tn2_kernel(TnArgs a) {
   constexpr int SK = 16, LW = SK + 2;
   if (a.prio) __builtin_amdgcn_s_setprio(2);
-  typedef typename AccT<F32>::type Acc;
+  typedef v4d Acc;    // FP64 accumulators (FP32 products are widened per slab)
+  typedef typename OpT<F32>::type Op;
   __shared__ double sA[2][128 * LW];
   __shared__ double sB[2][64 * LW];
   const int tp = blockIdx.x / a.tilesN, tn = blockIdx.x % a.tilesN, split = blockIdx.y;
@@ -426,7 +478,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
   const int ia0 = h * 64 + (w4 & 1) * 32, jb0 = (w4 >> 1) * 32;
   const int nfull = (int)((ke - kb) / SK);
   auto compute = [&](int buf) {
-    double xa[2][4], xb[2][4];
+    Op xa[2][4], xb[2][4];   // FP32 operands are rounded as they leave LDS
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const double* pa = &sA[buf][(ia0 + 16 * t + li) * LW + 4 * g];
@@ -436,12 +488,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
       xa[t][0] = a0.x; xa[t][1] = a0.y; xa[t][2] = a1.x; xa[t][3] = a1.y;
       xb[t][0] = b0.x; xb[t][1] = b0.y; xb[t][2] = b1.x; xb[t][3] = b1.y;
     }
+    [[maybe_unused]] v4f t32[2][2];
+    if constexpr (F32)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) t32[x][y] = v4f{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+        for (int y = 0; y < 2; ++y) {
+          if constexpr (F32)
+            t32[x][y] = mfma(xb[y][s], xa[x][s], t32[x][y]);
+          else
+            acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+        }
+    if constexpr (F32)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) widen_add(acc[x][y], t32[x][y]);
   };
   auto koff = [&](int sl) { return kb + (int64_t)std::min(sl, nfull - 1) * SK; };
   v2d ra0[2], rb0, ra1[2], rb1;
@@ -495,7 +563,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 4))) voi
     compute(buf);
   }
   if (tm < a.ntiles / a.tilesN)
-    tn_store(a, acc, tm * a.tilesN + tn, split, w4, lane, tm * 64 + (w4 & 1) * 32, tn * 64 + jb0);
+    tn_store(a, acc, tm * a.tilesN + tn, split, w4, lane, tm * 64 + (w4 & 1) * 32, tn * 64 + jb0, F32);
 }
 
 // Fallback for operands that are not 16-byte aligned or have odd leading
@@ -543,7 +611,7 @@ __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
   }
-  tn_store(a, acc, tile, split, wave, lane, i0, j0);
+  tn_store(a, acc, tile, split, wave, lane, i0, j0, false);
 }
 
 // Sum the split partials in split order; write C (and C2 +=).  One block per
@@ -664,9 +732,15 @@ void launch_tn_reduce(const TnArgs& a, hipStream_t st) {
 // Upper Cholesky factor of a panel leaf's Gram matrix W (w <= kLeaf), its
 // inverse, and on the second pass R2 R1 and the lookahead coefficients T^T X.
 // One block of four waves (see chol_blocked for the factorization).  A
-// non-positive pivot sets info[0] = 1 + panel (first occurrence kept) and the
-// factorization continues with pivot 1.
+// pivot at most kCholBreak times its column's diagonal entry is a breakdown,
+// handled by the column-wise fallback described at chol_body.
 // --------------------------------------------------------------------------
+
+// Smallest pivot / diagonal ratio a Cholesky-QR pass accepts: below it a
+// column lies within 1e-7 rad of the span of the columns before it, the
+// panel's condition number exceeds ~1e7, and one Cholesky-QR pass could no
+// longer bring the panel close enough to orthonormal for the second to finish.
+constexpr double kCholBreak = 1e-14;
 
 
 // 1/sqrt(x) to full double precision: hardware estimate plus one Newton step.
@@ -703,7 +777,7 @@ __device__ __forceinline__ void mma16(v4d& acc, int lane, int nk, FA A, FB B) {
 // column-j factors, and subtracts.  Only the wave's own LDS traffic orders the
 // steps (in-order LDS within a wave), so there is no block barrier.
 __device__ __forceinline__ void chol_diag16(int lane, int o, double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1],
-                                            double* prow, bool& bad) {
+                                            double* prow, const double* dg, bool& bad) {
   const int tx = lane & 15;
   const bool dl = lane < 16, zl = lane >= 16 && lane < 32;
   double c[16];
@@ -719,7 +793,10 @@ __device__ __forceinline__ void chol_diag16(int lane, int o, double (*Rl)[kLeaf 
 #pragma unroll
     for (int i = j + 1; i < 16; ++i) fac[i] = prow[i];
     __builtin_amdgcn_wave_barrier();
-    if (!(piv > 0.0) || !isfinite(piv)) {
+    // breakdown: a pivot that is not positive, or below kCholBreak times the
+    // column's diagonal entry in the Gram matrix (the column lies within an
+    // angle of 1e-7 of the span of the columns before it)
+    if (!(piv > kCholBreak * dg[o + j]) || !isfinite(piv)) {
       bad = true;
       piv = 1.0;
     }
@@ -740,12 +817,12 @@ __device__ __forceinline__ void chol_diag16(int lane, int o, double (*Rl)[kLeaf 
 // wave: T_ab = -T_aa sum_{c=a+1..b} R_ac T_cb for a = b-1 down to 0.  About a
 // dozen block barriers instead of one per pivot.
 __device__ __forceinline__ void chol_blocked(int tid, double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1],
-                                             double* prow, bool& bad) {
+                                             double* prow, const double* dg, bool& bad) {
   const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
 #pragma unroll 1
   for (int b = 0; b < 4; ++b) {
     const int o = 16 * b;
-    if (wave == 0) chol_diag16(lane, o, Rl, Tl, prow, bad);
+    if (wave == 0) chol_diag16(lane, o, Rl, Tl, prow, dg, bad);
     __syncthreads();
     // row panel R_bc = T_bb^T W_bc, in place
     const int c = b + 1 + wave;
@@ -846,14 +923,42 @@ __device__ __forceinline__ void lds_mm_store(int tid, const double (*Al)[kLeaf +
 // column group cg & 1).  The 64 x 16 strip of W is summed in split order into
 // LDS (or read from a.C, where a product without a split stored it) and
 // multiplied by T^T on MFMA, wave v forming rows 16v .. 16v + 15.
+// When the panel's second pass took the column-wise fallback (*fb set), the
+// finished panel is no longer P1 T, and the strip's coefficients are formed
+// directly as P^T Q_t over the a.K rows (P: ld ldp, Q_t = a.B), on MFMA with
+// operands read straight from memory (a rare path; its speed does not
+// matter).
 __global__ __launch_bounds__(256) void tn_reduce_tmul_kernel(TnArgs a, const double* T, int w, double* out,
-                                                             int64_t ldo) {
+                                                             int64_t ldo, const int* fb, const double* P,
+                                                             int64_t ldp) {
   __shared__ double Wl[kLeaf][16 + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
   const int tile = blockIdx.x >> 2, cg = blockIdx.x & 3, tid = threadIdx.x;
   const int lane = tid & 63, li = lane & 15, g = lane >> 4;
   const int64_t jc = (int64_t)tile * kTile + (cg >> 1) * 32 + 16 * (cg & 1);   // first column of the strip
   const int wc = (int)std::max<int64_t>(0, std::min<int64_t>(16, a.N - jc));
+  if (fb && *fb) {
+    const int wave = tid >> 6;
+    const int i = 16 * wave + li, j = li;
+    const double* pa = P + (int64_t)(i < w ? i : 0) * ldp;
+    const double* pb = a.B + (jc + (j < wc ? j : 0)) * a.ldb;
+    v4d acc = v4d{0, 0, 0, 0};
+    for (int64_t k0 = 0; k0 < a.K; k0 += 16) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t k = k0 + 4 * g + s;
+        const double xa = (k < a.K && i < w) ? pa[k] : 0.0;
+        const double xb = (k < a.K && j < wc) ? pb[k] : 0.0;
+        acc = mfma(xb, xa, acc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jj = 4 * r + g;
+      if (i < w && jj < wc) out[i + (jc + jj) * ldo] = acc[r];
+    }
+    return;
+  }
   double tv[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -903,9 +1008,10 @@ __global__ __launch_bounds__(256) void tn_reduce_tmul_kernel(TnArgs a, const dou
   }
 }
 
-void launch_tn_reduce_tmul(const TnArgs& a, const double* T, int w, double* out, int64_t ldo, hipStream_t st) {
+void launch_tn_reduce_tmul(const TnArgs& a, const double* T, int w, double* out, int64_t ldo, hipStream_t st,
+                           const int* fb, const double* P, int64_t ldp) {
   if (a.M <= 0 || a.N <= 0) return;
-  hipLaunchKernelGGL(tn_reduce_tmul_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w, out, ldo);
+  hipLaunchKernelGGL(tn_reduce_tmul_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w, out, ldo, fb, P, ldp);
 }
 
 // C = T^T X with T (64 x 64, upper triangular, row-major LDS) and X (w x w,
@@ -952,16 +1058,62 @@ __device__ __forceinline__ void tmul_global_store(int tid, const double (*Tl)[kL
     }
 }
 
+// Breakdown fallback of the second pass: the column-wise CGS2 product
+// out (w x wn, ld ldo) = P^T Qn over mrows rows, one column of Qn per
+// workgroup pass (the coefficients of the next panel against the panel the
+// fallback orthogonalised).
+template <int NT>
+__device__ void colwise_product_store(double* P, int64_t ldp, int64_t mrows, int w, const double* Qn,
+                                      int64_t ldqn, int wn, double* out, int64_t ldo, ColwiseLds<NT>& L) {
+  const int tid = threadIdx.x;
+  for (int jn = 0; jn < wn; ++jn) {
+    for (int c0 = 0; c0 < w; c0 += kColChunk)
+      colwise_dots<NT>(P, ldp, mrows, c0, min(w, c0 + kColChunk), Qn + (int64_t)jn * ldqn, L.s1, nullptr, -1,
+                       1.0, L);
+    if (tid < w) out[tid + jn * ldo] = L.s1[tid];
+    __syncthreads();
+  }
+}
+
+// The second pass's breakdown fallback, kept out of line so that its loops
+// do not add to the registers of the Cholesky path: CGS2 of the panel into
+// Rl, and the next panel's coefficients P^T Q_next when Rbar is given.
+// Returns false for a zero column (exact rank deficiency).
+__device__ __attribute__((noinline)) bool chol_fallback(const CholArgs& a, double (*Rl)[kLeaf + 1],
+                                                        ColwiseLds<256>* L) {
+  const bool ok = colwise_panel<256>(a.P, a.ldp, a.mrows, a.w, COLWISE_CGS2, 0.0, Rl, *L);
+  if (a.X)
+    colwise_product_store<256>(a.P, a.ldp, a.mrows, a.w, a.P + (int64_t)a.w * a.ldp, a.ldp, a.w, a.Rbar, a.ldr,
+                               *L);
+  return ok;
+}
+
 // The kernel body on caller-provided LDS (Rl, Tl: 64 x 65 each; prow: 16;
-// flags: 2 ints).  PASS1_ONLY drops the second-pass code.
+// dg: 64; flags: 3 ints; L: the column-wise routine's reduction space, pass 2
+// only).  PASS1_ONLY drops the second-pass code.
+//
+// Breakdown (a Cholesky pivot at most kCholBreak times its diagonal entry):
+// on the first pass R1 = T1 = I are returned, so the transform leaves the
+// panel as it is, and the breakdown is flagged in info[1]; on the second pass
+// (flagged, or breaking down itself) the panel is orthogonalised column by
+// column by CGS2 in this workgroup, T = I is returned, R_panel = R_cgs2 R1,
+// the next panel's coefficients are computed from the finished panel
+// directly, the panel is marked in a.fb for the update that started from its
+// first pass, and info[2] counts the fallback.  Only a panel that is exactly
+// rank-deficient (a zero column after projection) sets info[0].
 template <bool PASS1_ONLY>
 __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf + 1], double (*Tl)[kLeaf + 1],
-                                          double* prow, int* flags) {
+                                          double* prow, double* dg, int* flags, ColwiseLds<256>* L) {
   const int pass = PASS1_ONLY ? 1 : a.pass;
   int& s_exact = flags[0];
   int& s_bad = flags[1];
+  int& s_fb = flags[2];
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6, w = a.w;
-  if (tid == 0) { s_exact = (pass == 1); s_bad = 0; }
+  if (tid == 0) {
+    s_exact = (pass == 1);
+    s_bad = 0;
+    s_fb = pass == 2 ? a.info[1] : 0;
+  }
   // W (w x w) into Rl, identity-padded: all loads issued first
   {
     double v[16];
@@ -975,15 +1127,18 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
     for (int q = 0; q < 16; ++q) {
       const int k = ty + 4 * q;
       Rl[tx][k] = v[q];
+      if (k == tx) dg[tx] = v[q];
       far |= !(fabs(v[q] - (tx == k ? 1.0 : 0.0)) <= 1e-8);
     }
     __syncthreads();
     if (pass == 2 && far) s_exact = 1;
   }
   __syncthreads();
-  if (s_exact) {
+  if (s_fb) {
+    // the first pass broke down: nothing to factor here
+  } else if (s_exact) {
     bool bad = false;
-    chol_blocked(tid, Rl, Tl, prow, bad);
+    chol_blocked(tid, Rl, Tl, prow, dg, bad);
     if (bad) s_bad = 1;
   } else {
     // W = I + E with |E| <= 1e-8: R = I + F, F = strict upper part of E plus
@@ -1004,6 +1159,35 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
     }
   }
   __syncthreads();
+  bool rank_deficient = false;
+  if (pass == 1 && s_bad) {
+    // leave the panel as it is: R1 = T1 = I; the second pass takes over
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = ty + 4 * q;
+      Rl[tx][k] = Tl[tx][k] = (tx == k) ? 1.0 : 0.0;
+    }
+    if (tid == 0) a.info[1] = 1;
+    __syncthreads();
+  }
+  if constexpr (!PASS1_ONLY) {
+    if (pass == 2 && (s_fb || s_bad)) {
+      // column-wise CGS2 of the panel in place: R_cgs2 into Rl, T = I, and
+      // the next panel's coefficients from the finished panel
+      rank_deficient = !chol_fallback(a, Rl, L);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = ty + 4 * q;
+        Tl[tx][k] = (tx == k) ? 1.0 : 0.0;
+      }
+      if (tid == 0) {
+        a.info[1] = 0;
+        a.info[2] += 1;
+        if (a.fb) *a.fb = 1;
+      }
+      __syncthreads();
+    }
+  }
   // T (and R1 on the first pass) to global, column-major w x w
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -1014,27 +1198,30 @@ __device__ __forceinline__ void chol_body(const CholArgs& a, double (*Rl)[kLeaf 
       if (pass == 2 && a.Tcopy) a.Tcopy[tx + k * w] = Tl[tx][k];
     }
   }
-  if (pass == 2) {
-    // R1 for R_panel = R2 R1, requested before T^T X so both loads overlap
-    double r1v[16];
+  if constexpr (!PASS1_ONLY) {
+    if (pass == 2) {
+      // R1 for R_panel = R2 R1, requested before T^T X so both loads overlap
+      double r1v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = ty + 4 * q;
-      r1v[q] = (tx < w && k < w) ? a.R1[tx + k * w] : (tx == k ? 1.0 : 0.0);
-    }
-    // the next panel's update coefficients: (P1 T)^T Q_next = T^T X
-    if (a.X) tmul_global_store(tid, Tl, a.X, a.ldx, w, a.Rbar, a.ldr);
-    // R_panel = R2 R1 with R1 staged in Tl (T is stored)
-    __syncthreads();
+      for (int q = 0; q < 16; ++q) {
+        const int k = ty + 4 * q;
+        r1v[q] = (tx < w && k < w) ? a.R1[tx + k * w] : (tx == k ? 1.0 : 0.0);
+      }
+      // the next panel's update coefficients: (P1 T)^T Q_next = T^T X (after a
+      // fallback they were formed from the finished panel itself)
+      if (a.X && !(s_fb || s_bad)) tmul_global_store(tid, Tl, a.X, a.ldx, w, a.Rbar, a.ldr);
+      // R_panel = R2 R1 with R1 staged in Tl (T is stored)
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = ty + 4 * q;
-      Tl[tx][k] = r1v[q];
+      for (int q = 0; q < 16; ++q) {
+        const int k = ty + 4 * q;
+        Tl[tx][k] = r1v[q];
+      }
+      __syncthreads();
+      lds_mm_store<false, true>(tid, Rl, Tl, w, w, a.Rout, a.ldr);
     }
-    __syncthreads();
-    lds_mm_store<false, true>(tid, Rl, Tl, w, w, a.Rout, a.ldr);
   }
-  if (tid == 0 && s_bad && *a.info == 0) *a.info = 1 + a.panel;
+  if (tid == 0 && rank_deficient && a.info[0] == 0) a.info[0] = 1 + a.panel;
 }
 
 __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
@@ -1042,8 +1229,28 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   __shared__ double Rl[kLeaf][kLeaf + 1];
   __shared__ double Tl[kLeaf][kLeaf + 1];
   __shared__ double prow[16];
-  __shared__ int flags[2];
-  chol_body<false>(a, Rl, Tl, prow, flags);
+  __shared__ double dg[kLeaf];
+  __shared__ int flags[3];
+  __shared__ ColwiseLds<256> L;
+  chol_body<false>(a, Rl, Tl, prow, dg, flags, &L);
+}
+
+// One workgroup orthogonalises a panel leaf column by column (the CGS2, ICGS
+// and MGS panel modes) and stores its R block.
+__global__ __launch_bounds__(512) void colpanel_kernel(ColArgs a) {
+  __builtin_amdgcn_s_setprio(2);   // panel chain
+  __shared__ double Rl[kLeaf][kLeaf + 1];
+  __shared__ ColwiseLds<512> L;
+  const bool ok = colwise_panel<512>(a.P, a.ldp, a.mrows, a.w, a.mode, a.eta, Rl, L);
+  for (int e = threadIdx.x; e < a.w * a.w; e += 512) {
+    const int i = e % a.w, j = e / a.w;
+    a.Rout[i + (int64_t)j * a.ldr] = Rl[i][j];
+  }
+  if (threadIdx.x == 0 && !ok && a.info[0] == 0) a.info[0] = 1 + a.panel;
+}
+
+void launch_colpanel(const ColArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(colpanel_kernel, dim3(1), dim3(512), 0, st, a);
 }
 
 CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
@@ -1054,13 +1261,18 @@ CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, 
   c.T = s.T; c.R1 = s.R1; c.Rout = Rout; c.ldr = ldr; c.info = s.info;
   c.X = X; c.ldx = ldx; c.Rbar = Rbar;
   c.Tcopy = nullptr;
+  c.P = nullptr; c.ldp = 0; c.mrows = 0;
+  c.fb = nullptr;
   return c;
 }
 
 void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st, double* Tcopy) {
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st, double* Tcopy, double* P,
+                 int64_t ldp, int64_t mrows, int* fb) {
   CholArgs c = chol_args(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s);
   c.Tcopy = Tcopy;
+  c.P = P; c.ldp = ldp; c.mrows = mrows;
+  c.fb = fb;
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, st, c);
 }
 
@@ -1245,10 +1457,10 @@ __device__ __forceinline__ void nn_mma(Acc (&acc)[4], const double (*sBb)[64 + 1
 // compiles to more registers than the straight-line one (three waves per SIMD
 // instead of four), and measured faster in the factorization: the update's
 // blocks leave more room for the panel chain's kernels that run beside them.
-template <int TAG, bool F32>
+template <int TAG>
 __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
   if (a.prio) __builtin_amdgcn_s_setprio(2);
-  typedef typename AccT<F32>::type Acc;
+  typedef v4d Acc;
   __shared__ double sB[NK][64 + 1];
   for (int blk = blockIdx.x; blk < a.ntiles; blk += gridDim.x) {
     int tm, tn;
@@ -1257,7 +1469,7 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
     double cval[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
+      const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, false);
       cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
     }
     double xa[16];
@@ -1281,7 +1493,7 @@ __global__ __launch_bounds__(256) void nn1_kernel(NnArgs a) {
       for (int y = 0; y < 4; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int j = t.jb + 16 * y + colsub(r, t.g, F32);
+          const int j = t.jb + 16 * y + colsub(r, t.g, false);
           if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
         }
     }
@@ -1351,7 +1563,7 @@ __global__ __launch_bounds__(256) void nn1_apply_kernel(NnArgs a, const double* 
 }
 
 bool launch_nn1_apply(const NnArgs& a, const double* T, int w, hipStream_t st) {
-  if (a.M <= 0 || a.N <= 0 || a.K != w || w > NK || a.tilesN != 1 || a.f32) return false;
+  if (a.M <= 0 || a.N <= 0 || a.K != w || w > NK || a.tilesN != 1) return false;
   hipLaunchKernelGGL(nn1_apply_kernel, dim3(a.ntiles), dim3(256), 0, st, a, T, w);
   return true;
 }
@@ -1361,9 +1573,9 @@ bool launch_nn1_apply(const NnArgs& a, const double* T, int w, hipStream_t st) {
 // the block's K range is one split and its partial tile is stored for
 // nn_reduce_kernel; otherwise C is updated in place (the path for operands
 // nnw_kernel does not take).
-template <bool SPLIT, int TAG, bool F32>
+template <bool SPLIT, int TAG>
 __device__ __forceinline__ void nn_body(const NnArgs& a, double (*sB)[NK][64 + 1], int bx, int split) {
-  typedef typename AccT<F32>::type Acc;
+  typedef v4d Acc;
   int tm = bx / a.tilesN, tn = bx % a.tilesN;
   if (!SPLIT) xcd_tile(bx, a.ntiles, a.ntiles / a.tilesN, a.tilesN, tm, tn);
   const NnTile t = nn_tile_at(a, tm, tn);
@@ -1376,7 +1588,7 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, double (*sB)[NK][64 + 1
   if (!SPLIT) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, F32);
+      const int j = t.jb + 16 * (e >> 2) + colsub(e & 3, t.g, false);
       cval[e] = a.C[t.ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
     }
   }
@@ -1434,16 +1646,16 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, double (*sB)[NK][64 + 1
   for (int y = 0; y < 4; ++y)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j = t.jb + 16 * y + colsub(r, t.g, F32);
+      const int j = t.jb + 16 * y + colsub(r, t.g, false);
       if (j < a.N) a.C[t.i + (int64_t)j * a.ldc] = cval[y * 4 + r] - acc[y][r];
     }
 }
 
-template <bool SPLIT, int TAG, bool F32>
+template <bool SPLIT, int TAG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nn_kernel(NnArgs a) {
   if (a.prio) __builtin_amdgcn_s_setprio(2);
   __shared__ double sB[2][NK][64 + 1];
-  nn_body<SPLIT, TAG, F32>(a, sB, blockIdx.x, blockIdx.y);
+  nn_body<SPLIT, TAG>(a, sB, blockIdx.x, blockIdx.y);
 }
 
 // The re-projection update P -= Q S, split over K, with one extra block that
@@ -1458,14 +1670,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   __builtin_amdgcn_s_setprio(2);
   __shared__ double smem[2 * NK * (64 + 1)];
   __shared__ double prow[16];
-  __shared__ int flags[2];
+  __shared__ double dg[kLeaf];
+  __shared__ int flags[3];
   if ((int)blockIdx.x == a.ntiles) {
     if (blockIdx.y == 0)
       chol_body<true>(c, reinterpret_cast<double (*)[kLeaf + 1]>(smem),
-                      reinterpret_cast<double (*)[kLeaf + 1]>(smem + kLeaf * (kLeaf + 1)), prow, flags);
+                      reinterpret_cast<double (*)[kLeaf + 1]>(smem + kLeaf * (kLeaf + 1)), prow, dg, flags,
+                      nullptr);
     return;
   }
-  nn_body<true, TAG_REPROJ, false>(a, reinterpret_cast<double (*)[NK][64 + 1]>(smem), blockIdx.x, blockIdx.y);
+  nn_body<true, TAG_REPROJ>(a, reinterpret_cast<double (*)[NK][64 + 1]>(smem), blockIdx.x, blockIdx.y);
 }
 
 // C -= sum of the split partials (split order).  One block per wave of a
@@ -1482,7 +1696,7 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
   double old[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int j = jq + colsub(u, g, a.f32);
+    const int j = jq + colsub(u, g, false);
     old[u] = a.C[ic + (int64_t)(j < a.N ? j : 0) * a.ldc];
   }
   double v[4];
@@ -1490,7 +1704,7 @@ __global__ __launch_bounds__(256) void nn_reduce_kernel(NnArgs a) {
   if (!aok) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int j = jq + colsub(u, g, a.f32);
+    const int j = jq + colsub(u, g, false);
     if (j < a.N) a.C[i + (int64_t)j * a.ldc] = old[u] - v[u];
   }
 }
@@ -1554,15 +1768,14 @@ __global__ __launch_bounds__(256) void nn_reduce_apply_kernel(NnArgs a, const do
 }
 
 bool launch_nn_reduce_apply(const NnArgs& a, const double* T, int w, double* X, int64_t ldx, hipStream_t st) {
-  if (a.M <= 0 || a.nsplit <= 1 || a.tilesN != 1 || a.N != w || w > kLeaf || a.f32) return false;
+  if (a.M <= 0 || a.nsplit <= 1 || a.tilesN != 1 || a.N != w || w > kLeaf) return false;
   hipLaunchKernelGGL(nn_reduce_apply_kernel, dim3(a.ntiles * 4), dim3(256), 0, st, a, T, w, X, ldx);
   return true;
 }
 
 NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
-                int N, int K, const Scratch& s, bool f32) {
+                int N, int K, const Scratch& s) {
   NnArgs a{};
-  a.f32 = f32;
   a.C = C; a.ldc = ldc; a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
   a.M = M; a.N = N; a.K = K;
   a.tilesN = (N + 63) / 64;
@@ -1595,9 +1808,9 @@ NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const doub
 // multiple of KC, 16-byte aligned A and B with even leading dimensions, and
 // an even M; tiles take the XCD-aware order.
 // The body for slabs of SK k-values (32 or 16; LDS row pitch SK + 2).
-template <int TAG, bool F32, int SK>
+template <int TAG, int SK>
 __device__ __forceinline__ void nnw_body(const NnArgs& a, double (*sA)[64 * (SK + 2)], double (*sB)[64 * (SK + 2)]) {
-  typedef typename AccT<F32>::type Acc;
+  typedef v4d Acc;
   constexpr int LW = SK + 2;         // padded LDS row (doubles)
   constexpr int NQ = SK / 8;         // v2d loads per thread and operand per slab
   constexpr int TPC = SK / 2;        // B staging: threads per column (one k pair each)
@@ -1613,7 +1826,7 @@ __device__ __forceinline__ void nnw_body(const NnArgs& a, double (*sA)[64 * (SK 
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
-    const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, F32);
+    const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, false);
     cval[e] = a.C[(i < a.M ? i : 0) + (j < a.N ? j : 0) * a.ldc];
   }
   // staging of A: thread loads one v2d (rows 2 ip, 2 ip + 1) of k rows kr + 8 q
@@ -1697,7 +1910,7 @@ __device__ __forceinline__ void nnw_body(const NnArgs& a, double (*sA)[64 * (SK 
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int x = e >> 3, y = (e >> 2) & 1, r = e & 3;
-    const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, F32);
+    const int64_t i = ib + ia0 + 16 * x + li, j = jb + jb0 + 16 * y + colsub(r, g, false);
     if (i < a.M && j < a.N) a.C[i + j * a.ldc] = cval[e] - acc[x][y][r];
   }
 }
@@ -1705,23 +1918,23 @@ __device__ __forceinline__ void nnw_body(const NnArgs& a, double (*sA)[64 * (SK 
 // 32-deep slabs, two waves per SIMD: the rank-64 trailing update, which runs
 // beside the panel chain (with 16-deep slabs and three waves per SIMD it is
 // faster alone but the step at n = 4096 was 3.8% slower).
-template <int TAG, bool F32>
+template <int TAG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void nnw_kernel(NnArgs a) {
   if (a.prio) __builtin_amdgcn_s_setprio(2);
   __shared__ double sA[2][64 * (32 + 2)];
   __shared__ double sB[2][64 * (32 + 2)];
-  nnw_body<TAG, F32, 32>(a, sA, sB);
+  nnw_body<TAG, 32>(a, sA, sB);
 }
 
 // 16-deep slabs (37 KB of LDS, 148-164 VGPRs), three waves per SIMD: K >= 128,
 // where the update is MFMA-bound in FP64.  Against the 32-deep form, 9% faster
 // alone at K = 128 and 8% at K = 256, and 4% off the n = 16384 step.
-template <int TAG, bool F32>
+template <int TAG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void nnw16_kernel(NnArgs a) {
   if (a.prio) __builtin_amdgcn_s_setprio(2);
   __shared__ double sA[2][64 * (16 + 2)];
   __shared__ double sB[2][64 * (16 + 2)];
-  nnw_body<TAG, F32, 16>(a, sA, sB);
+  nnw_body<TAG, 16>(a, sA, sB);
 }
 
 // Operands the LDS-staged update takes, K >= 64 (else the register-staged
@@ -1732,35 +1945,31 @@ static bool nnw_ok(const NnArgs& a) {
   return a.K >= NK && a.K % KC == 0 && a.M % 2 == 0 && aligned16(a.A, a.lda) && aligned16(a.B, a.ldb);
 }
 
-template <int TAG, bool F32>
+template <int TAG>
 static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
   if (a.K <= NK && !nnw_ok(a))
-    hipLaunchKernelGGL((nn1_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nn1_kernel<TAG>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (a.nsplit > 1)
-    hipLaunchKernelGGL((nn_kernel<true, TAG, F32>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nn_kernel<true, TAG>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
   else if (nnw_ok(a) && a.K >= 2 * NK)
-    hipLaunchKernelGGL((nnw16_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nnw16_kernel<TAG>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (nnw_ok(a))
-    hipLaunchKernelGGL((nnw_kernel<TAG, F32>), dim3(a.ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nnw_kernel<TAG>), dim3(a.ntiles), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((nn_kernel<false, TAG, F32>), dim3(a.ntiles, 1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((nn_kernel<false, TAG>), dim3(a.ntiles, 1), dim3(256), 0, st, a);
 }
 
 void launch_nn_product(const NnArgs& a, int tag, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.K <= 0) return;
-  if (a.f32) {
-    nn_launch_tag<TAG_TRAIL, true>(a, st);
-    return;
-  }
   switch (tag) {
-    case TAG_TRAIL: nn_launch_tag<TAG_TRAIL, false>(a, st); break;
-    case TAG_REPROJ: nn_launch_tag<TAG_REPROJ, false>(a, st); break;
-    default: nn_launch_tag<TAG_PANEL, false>(a, st); break;
+    case TAG_TRAIL: nn_launch_tag<TAG_TRAIL>(a, st); break;
+    case TAG_REPROJ: nn_launch_tag<TAG_REPROJ>(a, st); break;
+    default: nn_launch_tag<TAG_PANEL>(a, st); break;
   }
 }
 
 bool launch_nn_chol(const NnArgs& a, const CholArgs& c, hipStream_t st) {
-  if (a.M <= 0 || a.N <= 0 || a.K <= NK || a.nsplit <= 1 || a.f32 || c.w > kLeaf) return false;
+  if (a.M <= 0 || a.N <= 0 || a.K <= NK || a.nsplit <= 1 || c.w > kLeaf) return false;
   hipLaunchKernelGGL(nn_chol_kernel, dim3(a.ntiles + 1, a.nsplit), dim3(256), 0, st, a, c);
   return true;
 }

@@ -36,8 +36,8 @@ struct EncodeArgs {
   int64_t ld;
   int64_t m, n, bs, bw;
   int pr, pc, kv, kh;
-  // rows pass: g[k * pr + t] = g~_v[k][t];  columns pass: g[k * pc + t] = g~_h[t][k]
-  double g[kMaxGen * kMaxGrid];
+  double g[kMaxGen * kMaxGrid];    // row code: g[k * pr + t] = g~_v[k][t]
+  double gc[kMaxGen * kMaxGrid];   // column code: gc[l * kMaxGrid + t] = g~_h[t][l]
 };
 
 struct PostArgs {
@@ -63,7 +63,10 @@ struct FoldArgs {
 
 // Scratch regions inside the caller's workspace (all device pointers).
 struct Scratch {
-  int* info;          // [0]: breakdown flag (0 or 1 + panel)
+  int* info;          // [0]: 0, or 1 + the first panel that is exactly rank-deficient;
+                      // [1]: first Cholesky pass of the current leaf broke down;
+                      // [2]: leaves orthogonalised by the column-wise fallback
+  int* fb;            // per panel: 1 if its second pass took the column-wise fallback
   double* part;       // split-K partial tiles
   int64_t npart;      // capacity in tiles (of kTile*kTile doubles)
   double* S;          // projection coefficients (and the fused first-pass Gram)
@@ -90,7 +93,8 @@ struct TnArgs {
   int M2;             // only rows i < M2 are added into C2
   double* part;
   int vec;            // both operands 16-byte aligned with even leading dimensions
-  int f32;            // FP32 products (operands rounded), FP32 accumulation
+  int f32;            // FP32 products (operands rounded), FP32 sums over 16
+                      // k-values, FP64 sums across those groups
   int prio;           // raise the waves' issue priority (panel-chain products)
   int pair;           // two tile rows per 512-thread workgroup (tn2_kernel)
 };
@@ -98,8 +102,9 @@ struct TnArgs {
 // Choose the split of C = A^T B (stored to C; rows below M2 -- all rows
 // unless changed -- also added into C2 if C2 != nullptr).
 // force_split > 0 fixes the split count (capped by the partial capacity).
-// f32: the product in FP32 (operands rounded to FP32, FP32 accumulation), for
-// the mixed-precision trailing update.
+// f32: the product on FP32 MFMA (operands rounded to FP32, FP32 sums over 16
+// k-values, FP64 sums across them), for the mixed-precision coefficient
+// product R_bar = Qbar^T Q_t.
 TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
                 int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0, bool f32 = false);
 // The product; with nsplit == 1 it stores C (and C2) itself, else partials.
@@ -109,7 +114,10 @@ void launch_tn_reduce(const TnArgs& a, hipStream_t st);
 // out (w x N, ldo) = T^T W for the product W = A^T B of a (a.M = w <= 64 rows,
 // one tile row): W is summed from the split partials (nsplit > 1) or read from
 // a.C (nsplit == 1, where the product stored it); T is w x w (ld w).
-void launch_tn_reduce_tmul(const TnArgs& a, const double* T, int w, double* out, int64_t ldo, hipStream_t st);
+// fb, P, ldp: when *fb is set (the panel's second pass took the column-wise
+// fallback) out = P^T B is formed directly from the finished panel P instead.
+void launch_tn_reduce_tmul(const TnArgs& a, const double* T, int w, double* out, int64_t ldo, hipStream_t st,
+                           const int* fb = nullptr, const double* P = nullptr, int64_t ldp = 0);
 
 // C (M x N) -= A (M x K) B (K x N).
 struct NnArgs {
@@ -119,12 +127,13 @@ struct NnArgs {
   int64_t M; int N; int K;
   int kchunk; int nsplit; int tilesN; int ntiles;
   int vec;            // B 16-byte aligned with even ldb (vector B loads)
-  int f32;            // FP32 products (operands rounded), FP32 accumulation
   double* part;
   int prio;           // raise the waves' issue priority (panel-chain products)
 };
+// The update is FP64 in every precision mode: it is a column operation on the
+// encoded matrix and must keep the checksum relations to FP64 rounding.
 NnArgs nn_setup(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
-                int N, int K, const Scratch& s, bool f32 = false);
+                int N, int K, const Scratch& s);
 void launch_nn_product(const NnArgs& a, int tag, hipStream_t st);
 void launch_nn_reduce(const NnArgs& a, hipStream_t st);   // nsplit > 1 only
 
@@ -137,7 +146,20 @@ struct CholArgs {
   const double* X; int64_t ldx;     // pass 2, optional: w x w product P1^T Q_next
   double* Rbar;                     // T^T X (ld ldr)
   double* Tcopy;                    // pass 2, optional: second destination of T (w x w, ld w)
+  double* P; int64_t ldp; int64_t mrows;   // pass 2: the panel (for the column-wise fallback)
+  int* fb;                          // pass 2, optional: set to 1 when the fallback ran
 };
+
+// One panel leaf orthogonalised column by column (colpanel_kernel).
+enum : int { COLWISE_CGS2 = 0, COLWISE_ICGS = 1, COLWISE_MGS = 2 };
+struct ColArgs {
+  double* P; int64_t ldp; int64_t mrows;
+  int w, mode;                      // w <= kLeaf; mode: COLWISE_CGS2 / _ICGS / _MGS
+  double eta;                       // ICGS: reorthogonalise when ||p after|| < eta ||p before||
+  double* Rout; int64_t ldr;        // the panel's R block (w x w, zeros below the diagonal)
+  int* info; int panel;             // a zero column sets info[0] = 1 + panel
+};
+void launch_colpanel(const ColArgs& a, hipStream_t st);
 
 CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
                    int64_t ldx, double* Rbar, int panel, const Scratch& s);
@@ -146,9 +168,16 @@ CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, 
 // pass 1: R1 <- chol(W), T <- R1^{-1}.  pass 2: R2 <- chol(W), T <- R2^{-1},
 // Rout (ldr) <- R2 R1, and, if X != nullptr, Rbar (ldr) <- T^T X (X: w x w,
 // ld ldx).  On the second pass T is also stored to Tcopy when it is not
-// nullptr.  Breakdown sets info[0] = 1 + panel.
+// nullptr.
+// Breakdown (a pivot at most 1e-14 times its diagonal entry): pass 1 returns
+// R1 = T = I and flags info[1]; pass 2 (flagged or breaking down) then
+// orthogonalises the panel P (mrows x w, ld ldp) column by column with CGS2,
+// returns T = I, Rout = R_cgs2 R1, Rbar = P^T Q_next from the finished panel
+// (Q_next: the w columns after P), sets *fb (if given) and counts the
+// fallback in info[2]; a zero column after projection sets info[0].
 void launch_chol(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,
-                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st, double* Tcopy = nullptr);
+                 int64_t ldx, double* Rbar, int panel, const Scratch& s, hipStream_t st, double* Tcopy = nullptr,
+                 double* P = nullptr, int64_t ldp = 0, int64_t mrows = 0, int* fb = nullptr);
 
 // The split re-projection update (launch_nn_product with nsplit > 1) with the
 // first Cholesky pass described by c run by one extra block of the same
@@ -169,8 +198,10 @@ void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s
 
 void launch_zero_ints(int* p, int n, hipStream_t st);
 void launch_fill_zero(double* p, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);
+// checksum rows only (a.kv rows of the code g over a.n columns)
 void launch_encode_rows(const EncodeArgs& a, hipStream_t st);
-void launch_encode_cols(const EncodeArgs& a, hipStream_t st);
+// the whole encoding in one pass: checksum rows (g), columns (gc) and corner
+void launch_encode_fused(const EncodeArgs& a, hipStream_t st);
 void launch_line(const LineArgs& a, hipStream_t st);
 void launch_erase(const EraseArgs& a, hipStream_t st);
 void launch_postorth(const PostArgs& a, hipStream_t st);

@@ -23,10 +23,10 @@ def make_inputs(n, pr, K, b, storage="out", seed=0, m=None, pc=None, kh=None, ki
     return A, v, gh, lay
 
 
-def gpu_config(cqr, lay, b, reproject=1, precision=0, lookahead=1):
+def gpu_config(cqr, lay, b, reproject=1, precision=0, lookahead=1, panel=0, icgs_eta=0.0):
     return cqr.Config(lay.m, lay.n, lay.pr, lay.pc, lay.kv, lay.kh, b,
                       cqr.CQR_IN_NODE if lay.storage == "in" else cqr.CQR_OUT_OF_NODE, reproject, precision,
-                      lookahead)
+                      lookahead, panel, icgs_eta)
 
 
 def oracle_state(A, v, gh, lay, b, k, panel="cgs2", reproject=True):

@@ -76,6 +76,21 @@ def test_plan_generators_and_tolerance_match_oracle(pr, pc, kv, kh, storage):
         assert cqr.coded_qr_plan_ftol(p) == f
         ws = cqr.coded_qr_workspace_bytes(p)
         assert ws > 0 and ws % 8 == 0
+        # placement: the storers the oracle's node map gives (whose load balance
+        # and exclusion are pinned to their definitions in the oracle tests),
+        # and the R code excludes the storer's own block column
+        qrow, rcol = cqr.coded_qr_plan_placement(p, cfg)
+        lay = oc.Layout(m, n, pr, pc, kv, kh, sname)
+        if storage == "in":
+            for k in range(kv):
+                holders = {i for i in range(pr) if (pr + k, 0) in lay.node_blocks((i, 0))[0]}
+                assert holders == {int(qrow[k])}
+            for k in range(kh):
+                holders = {j for j in range(pc) if (0, pc + k) in lay.node_blocks((0, j))[1]}
+                assert holders == {int(rcol[k])}
+                assert gh[rcol[k], k] == 0.0
+        else:
+            assert list(qrow) == [pr + k for k in range(kv)] and list(rcol) == [pc + k for k in range(kh)]
     finally:
         cqr.coded_qr_plan_destroy(p)
 
@@ -90,6 +105,10 @@ def test_plan_generators_and_tolerance_match_oracle(pr, pc, kv, kh, storage):
     dict(precision=7),              # unknown precision
     dict(precision=2),              # reserved precision
     dict(storage=5),                # unknown storage
+    dict(panel=4),                  # unknown panel mode
+    dict(icgs_eta=1.5),             # ICGS threshold above 1
+    dict(icgs_eta=-0.1),            # negative ICGS threshold
+    dict(icgs_eta=float("nan")),
 ])
 def test_plan_create_rejects_invalid_configs(bad):
     base = dict(m=256, n=256, pr=4, pc=4, kv=1, kh=1, b=16)

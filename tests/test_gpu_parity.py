@@ -37,6 +37,9 @@ SHAPES = [
     # products and re-projections, also with a 48-row last tile (b = 240)
     ("panel256", 1024, 4, 1, 256, "out", {}),
     ("ragged_panel240", 960, 4, 1, 240, "out", {}),
+    # three tile rows (odd): the last workgroup of the two-tile-row product
+    # computes an empty second half; its trailing products split over K
+    ("odd_tile_rows192", 768, 4, 1, 192, "out", {}),
 ]
 
 
