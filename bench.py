@@ -1,19 +1,25 @@
 """Benchmark of the coded-QR hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5] [--legs fp64,fp32]
 
 One step = the whole path on one synthetic input already resident in HBM:
 place A into the encoded buffer, encode, factor with the workload's scheduled
 node failures (erase + recover at the start of the scheduled panels),
 post-orthogonalize Q_1 and the right-hand side.  Prints ONE JSON line.
 
+The default workload is the largest one-GPU configuration: n = 32768
+Gaussian, 16 x 16 grid, b = 256, K = 8 in-node checksums, a reverse-diagonal
+storm of f_tol = 4 failures per grid line every 16 panels.  Each precision leg
+(FP64; the coefficient product R_bar on FP32 MFMA) runs the same input and
+schedule; `value` is the first leg's rate.
+
 value = coded-QR TFLOP/s = model flops / step time, with the model
 F = m' (4 n^2 + 4 n d + 4 n b) (right-looking update incl. carried checksum
-columns, left re-projection, CGS2 panels).  Also reported: the coding
+columns, left re-projection, CGS2 panels).  Also reported per leg: the coding
 overhead over the uncoded factorization (same library, K = 0) next to its
 algorithmic floor (1 + c/m)(1 + d/n) - 1, recovery time per failure event,
-error norms, the roofline of the dominant kernel measured with HIP events on
-the library's stream, and the FP64 CPU oracle timed on the host cores.
+error norms; the roofline of the dominant kernel measured with HIP events on
+the library's stream; and the FP64 CPU oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -40,10 +46,10 @@ WORKLOADS = {
     "c2": dict(n=4096, pr=8, K=2, b=64, storage="in", kind="random", nfail=2,
                desc="n=4096 Gaussian FP64, 8x8 grid (512x512 blocks), b=64, K=2 in-node checksums (f_tol=1), "
                     "2 random node failures at random panels"),
-    "c3": dict(n=16384, pr=8, K=4, b=128, storage="out", kind="revdiag", nfail=4,
+    "c3": dict(n=16384, pr=8, K=4, b=128, storage="out", kind="revdiag", nfail=4, cpu_sample_n=4096,
                desc="n=16384 Gaussian FP64, 8x8 grid (2048x2048 blocks), b=128, K=4 out-of-node (f_tol=4), "
                     "reverse-diagonal failures every 16 panels"),
-    "c5": dict(n=32768, pr=16, K=8, b=256, storage="in", kind="revdiag", nfail=4,
+    "c5": dict(n=32768, pr=16, K=8, b=256, storage="in", kind="revdiag", nfail=4, cpu_sample_n=8192,
                desc="n=32768 Gaussian FP64, 16x16 grid (2048x2048 blocks), b=256, K=8 in-node (f_tol=4), "
                     "reverse-diagonal failures every 16 panels"),
 }
@@ -57,13 +63,12 @@ SINGLE_KERNEL_PHASES = ("trailing_product", "trailing_update", "reproj_product",
                         "postorth")
 KERNEL_OF = {
     "encode": "encode_rows_kernel / encode_cols_kernel",
-    "reproj_product": "tn_lds_kernel<1, false>", "reproj_update": "nn_kernel<*, 1, false>",
+    "reproj_product": "tn_lds_kernel<1, false>", "reproj_update": "nn_kernel<*, 1>",
     "panel_gram": "tn_lds_kernel<2, false>", "panel_chol": "chol_kernel", "panel_transform": "apply_kernel / nn1_apply_kernel",
     "inpanel_projection": "tn/nn <2, false>",
-    "trailing_product": "tn_lds_kernel<0, false>", "trailing_update": "nnw_kernel<0, false>",
+    "trailing_product": "tn_lds_kernel<0, false>", "trailing_update": "nnw_kernel<0>",
     "split_reduce": "tn_reduce_kernel / nn_reduce_kernel", "recover": "line_kernel",
     "postorth": "postorth_kernel", "erase": "erase_kernel", "other": "zero_ints_kernel / fill_zero_kernel",
-    "panel_reencode": "encode_rows_kernel (one panel)",
     "solve": "trinv_kernel / gemv_t_kernel / trsv_step_kernel",
 }
 
@@ -426,9 +431,12 @@ def run_generator_study(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
+    ap.add_argument("--legs", default="fp64,fp32",
+                    help="comma-separated precision legs timed on the same input and schedule; the first gives "
+                         "`value` (fp64: FP64 throughout; fp32: the coefficient product R_bar on FP32 MFMA)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip overhead/profile/oracle legs")
@@ -436,7 +444,7 @@ def main():
                     help="after the run, launch one plain copy kernel of 512 MiB (y = 2x) as the reference for "
                          "HBM byte counters")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"),
-                    help="fp32: trailing-update products in FP32 on MFMA (everything else FP64)")
+                    help="--adjoint only: fp32 runs the forward's coefficient products on FP32 MFMA")
     ap.add_argument("--cond", type=float, default=0.0,
                     help="> 0: A = U diag(s) V^T with Haar U, V and log-spaced s of this condition number "
                          "instead of a Gaussian A")
@@ -449,7 +457,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the benchmark line: forward + adjoint of the tall-skinny least-squares "
                          "workload (m = 65536, n = 512), one JSON line")
-    ap.add_argument("--reps", type=int, default=5, help="repetitions of each timed extra (overhead legs)")
+    ap.add_argument("--reps", type=int, default=0,
+                    help="repetitions of each timed extra (overhead legs); 0: 2 from n = 16384 on, else 5")
     ap.add_argument("--generator-study", action="store_true",
                     help="host only: smallest |det| and largest condition number over all square submatrices of "
                          "the structured and of a random Q-side generator (f = 2..6, p_r = 16, 32, 64)")
@@ -487,199 +496,202 @@ def main():
     w = WORKLOADS[args.workload]
     n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
     storage = cqr.CQR_IN_NODE if w["storage"] == "in" else cqr.CQR_OUT_OF_NODE
-    prec = cqr.CQR_TRAIL_FP32 if args.precision == "fp32" else cqr.CQR_FP64
-    cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead, precision=prec)
+    legs = [x for x in args.legs.split(",") if x]
+    if not legs or any(x not in PRECISIONS for x in legs):
+        raise SystemExit(f"--legs takes a comma-separated list of {sorted(PRECISIONS)}")
     v = synth.q_generator_draws(K, pr, args.seed)
     gh = synth.r_generator_draws(pr, K, args.seed)
-    q = cqr.CodedQR(cfg, v, gh, dev)
-    ftol = q.ftol
+    cfg0 = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead)
+    q0 = cqr.CodedQR(cfg0, v, gh, dev)
+    ftol = q0.ftol
+    q0.close()
     inp = workload_inputs(args.workload, ftol, args.seed)
     A_host, rhs_host, sched = inp["A"], inp["rhs"], inp["schedule"]
     if args.cond > 0:
         A_host = conditioned_input(n, args.cond, args.seed, dev)
     A = cqr.to_device_colmajor(A_host, dev)
     B = cqr.to_device_colmajor(rhs_host, dev)
-    At, R = q.alloc()
-    Qpost = cqr.col_major(n, n, dev)
-    Bpost = cqr.col_major(n, 1, dev)
-
-    def step():
-        At[:n, :n].copy_(A)
-        q.encode(At)
-        k = 0
-        for t, nodes in list(sched) + [(cfg.npanels, None)]:
-            q.factor(At, R, k, t)
-            k = t
-            if nodes is None:
-                break
-            q.erase(At, R, nodes)
-            q.recover(At, R, nodes)
-        q.postorth(At, Qpost, B, Bpost)
+    mp, d = cfg0.mp, cfg0.N - n
+    F = model_flops(mp, n, d, b)
+    floor = (1 + (mp - n) / n) * (1 + d / n) - 1
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"{args.warmup} warmup steps done")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
-    log(f"{args.steps} timed steps done: {ms:.3f} ms per step")
-    mp, d = cfg.mp, cfg.N - n
-    F = model_flops(mp, n, d, b)
-    value = F / (ms * 1e-3) / 1e12
-
+    log(f"workload {args.workload}: inputs resident, legs {legs}")
+    reps = args.reps if args.reps > 0 else (2 if n >= 16384 else 5)
     out = {
-        "metric": "coded-QR TFLOP/s (+ overhead vs uncoded)",
-        "value": round(value, 4),
+        "metric": "coded-QR TFLOP/s + overhead vs uncoded; mixed vs FP64 at stated ||I-Q^TQ||",
+        "value": None,
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 trailing update / f64",
+        "dtype": PRECISIONS[legs[0]]["dtype"],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "n": n, "grid": f"{pr}x{pr}", "b": b,
                    "K": K, "f_tol": ftol, "storage": w["storage"], "panel": "CholQR2 (block CGS2) + re-projection",
-                   "lookahead": args.lookahead, "precision": args.precision,
+                   "lookahead": args.lookahead, "legs": legs,
                    "input": "gaussian" if args.cond <= 0 else f"U diag(s) V^T, cond {args.cond:g}",
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched],
-                   "model_flops": F, "wall_s_timed": round(wall, 3)},
+                   "model_flops": F, "uncoded_model_flops": model_flops(n, n, 0, b)},
+        "legs": {},
     }
+    first = None        # Q~ and R of the first leg, to compare the other legs with
+    At = R = Qpost = Bpost = None
+    for li, leg in enumerate(legs):
+        cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead,
+                         precision=PRECISIONS[leg]["code"])
+        q = cqr.CodedQR(cfg, v, gh, dev)
+        if At is None:
+            At, R = q.alloc()
+            Qpost = cqr.col_major(n, n, dev)
+            Bpost = cqr.col_major(n, 1, dev)
 
-    # errors of the last step (verification, not timed)
-    Qt = At[:, :n]
-    res = (torch.linalg.norm(A - At[:n, :n] @ R[:, :n]) / torch.linalg.norm(A)).item()
-    orth = torch.linalg.norm(torch.eye(n, device=dev, dtype=torch.float64) - Qt.T @ Qt).item()
-    orth_p = torch.linalg.norm(torch.eye(n, device=dev, dtype=torch.float64) - Qpost.T @ Qpost).item()
-    out["errors"] = {"residual": res, "orth_coded": orth, "orth_post": orth_p, "info": q.info()}
-
-    if not args.no_extras:
-        def timed(fn, reps=args.reps):
-            fn()
-            torch.cuda.synchronize()
-            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(reps):
-                fn()
-            z.record()
-            torch.cuda.synchronize()
-            return a.elapsed_time(z) / reps
-
-        def enc():
+        def step():
             At[:n, :n].copy_(A)
             q.encode(At)
+            k = 0
+            for t, nodes in list(sched) + [(cfg.npanels, None)]:
+                q.factor(At, R, k, t)
+                k = t
+                if nodes is None:
+                    break
+                q.erase(At, R, nodes)
+                q.recover(At, R, nodes)
+            q.postorth(At, Qpost, B, Bpost)
 
-        def fac():
-            q.factor(At, R)
-
-        t_enc = timed(enc)
-        t_fac = timed(lambda: (enc(), fac()))  - t_enc
-        t_post = timed(lambda: q.postorth(At, Qpost, B, Bpost))
-        # coded solve R_1 x = (G_0 Q_1)^T (G_0 b) on the last step's factors
-        X = cqr.col_major(n, 1, dev)
-        ws_solve = q.solve_workspace(1)
-
-        def solve():
-            q.solve(Qpost, R, Bpost, X, ws_solve)
-        t_solve = timed(solve)
-        x_direct = torch.linalg.solve(A, B)
-        out["solve"] = {"ms": round(t_solve, 4),
-                        "rel_err_vs_direct": (torch.linalg.norm(X - x_direct) / torch.linalg.norm(x_direct)).item()}
-        out["overhead"] = {
-            "T_enc_ms": round(t_enc, 4), "T_factor_coded_ms": round(t_fac, 4), "T_post_ms": round(t_post, 4),
-        }
-        log("coded legs done")
-
-        # profiled pass: per-kernel HIP events on the library's stream
-        q.profile(True)
-        step()
+        for _ in range(args.warmup):
+            step()
         torch.cuda.synchronize()
-        rep = q.profile_report()
-        q.profile(False)
-        phases = {k: {"ms": round(r["ms"], 4), "launches": r["launches"],
-                      "avg_us": round(1e3 * r["ms"] / max(r["launches"], 1), 3),
-                      "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3),
-                      "gbs": round(r["bytes"] / max(r["ms"], 1e-9) / 1e6, 1)}
-                  for k, r in rep.items() if r["launches"]}
-        out["phases"] = phases
-        nrec = sum(r["launches"] for r in rep.values())
-        rec_ms = rep["recover"]["ms"]
-        out["overhead"]["T_recov_ms_per_event"] = round(rec_ms / max(len(sched), 1), 4)
-        # the kernel holding the most time among phases that are exactly one
-        # kernel symbol (so rocprofv3's per-kernel average describes the same launches)
-        def kernel_of(phase):
-            k = KERNEL_OF[phase]
-            if phase == "trailing_update" and b >= 128:
-                k = "nnw16_kernel<0, false>"     # K = b >= 128: the 16-deep-slab form
-            if phase == "trailing_product" and b > 64:
-                # panels of several tile rows: two tile rows per workgroup (the
-                # last few products, with fewer tile columns, keep the one-tile
-                # kernels)
-                k = "tn2_kernel<0, false>"
-            # the trailing products are the FP32 instances in the mixed form
-            return k.replace("<0, false>", "<0, true>") if args.precision == "fp32" else k
-
-        dom = max((k for k in SINGLE_KERNEL_PHASES if rep[k]["launches"]), key=lambda k: rep[k]["ms"])
-        r = rep[dom]
-        # the trailing products run on FP32 MFMA in the mixed form, everything else on FP64
-        trail_fp32 = args.precision == "fp32" and dom in ("trailing_product", "trailing_update")
-        mfma_peak = PEAK["fp32_mfma_tflops" if trail_fp32 else "fp64_mfma_tflops"]
-        # the rank-b update moves 16 bytes (read and write of C) per 2b flops:
-        # MFMA-bound when b/8 flop/B exceeds the ridge peak / HBM bandwidth
-        update_mfma = dom == "trailing_update" and b / 8.0 > mfma_peak * 1e3 / PEAK["hbm_gbs"]
-        if dom in MFMA_PHASES or update_mfma:
-            ach = r["flops"] / (r["ms"] * 1e-3) / 1e12
-            pk = mfma_peak
-            roof = {"kernel": kernel_of(dom), "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
-                    "peak": pk, "unit": "TFLOP/s", "frac": round(ach / pk, 4)}
+        log(f"[{leg}] {args.warmup} warmup steps done")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / args.steps
+        log(f"[{leg}] {args.steps} timed steps done: {ms:.3f} ms per step")
+        L = {"ms_per_step": round(ms, 4), "tflops": round(F / (ms * 1e-3) / 1e12, 4),
+             "useful_tflops": round(model_flops(n, n, 0, b) / (ms * 1e-3) / 1e12, 4),
+             "wall_s_timed": round(wall, 3), "arithmetic": PRECISIONS[leg]["desc"]}
+        # errors of the last step (verification, outside the timed region)
+        Qt = At[:, :n]
+        eye = torch.eye(n, device=dev, dtype=torch.float64)
+        L["errors"] = {
+            "residual": (torch.linalg.norm(A - At[:n, :n] @ R[:, :n]) / torch.linalg.norm(A)).item(),
+            "orth_coded": torch.linalg.norm(eye - Qt.T @ Qt).item(),
+            "orth_post": torch.linalg.norm(eye - Qpost.T @ Qpost).item(),
+            "info": q.info()}
+        del eye
+        if first is None:
+            first = (At[:, :n].clone(), R.clone())
         else:
-            ach = r["bytes"] / (r["ms"] * 1e-3) / 1e9
-            roof = {"kernel": kernel_of(dom), "phase": dom, "bound": "hbm", "achieved": round(ach, 1),
-                    "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
-        roof["avg_launch_us"] = round(1e3 * r["ms"] / r["launches"], 3)
-        roof["launches"] = r["launches"]
-        roof["share_of_profiled_step"] = round(r["ms"] / sum(x["ms"] for x in rep.values()), 3)
-        roof["traffic"] = traffic_record(dom, args.workload) if args.precision == "fp64" else None
-        roof["events_per_step"] = 2 * nrec
-        out["roofline"] = roof
+            # against the first (FP64) leg on the same input and schedule; the
+            # FP64 leg matches the FP64 oracle in the parity tests
+            L["vs_" + legs[0] + "_leg"] = {
+                "R_max_rel": ((R - first[1]).abs().max() / first[1].abs().max()).item(),
+                "Q_max_abs": (At[:, :n] - first[0]).abs().max().item()}
+        log(f"[{leg}] errors {L['errors']}")
 
-        # uncoded: same library, K = 0.  The coded plan is released first: each
-        # plan's lookahead uses two streams of its own, and with both plans'
-        # streams alive there are more streams than the device's hardware
-        # queues (four by default), so the uncoded plan's two streams could
-        # share a queue and run one after the other.
+        if not args.no_extras:
+            def timed(fn, reps=reps):
+                fn()
+                torch.cuda.synchronize()
+                a0, z0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a0.record()
+                for _ in range(reps):
+                    fn()
+                z0.record()
+                torch.cuda.synchronize()
+                return a0.elapsed_time(z0) / reps
+
+            def enc():
+                At[:n, :n].copy_(A)
+                q.encode(At)
+
+            t_enc = timed(enc)
+            t_fac = timed(lambda: (enc(), q.factor(At, R))) - t_enc
+            t_post = timed(lambda: q.postorth(At, Qpost, B, Bpost))
+            L["overhead"] = {"T_enc_ms": round(t_enc, 4), "T_factor_coded_ms": round(t_fac, 4),
+                             "T_post_ms": round(t_post, 4)}
+            if li == 0:
+                # coded solve R_1 x = (G_0 Q_1)^T (G_0 b) on the last step's factors
+                X = cqr.col_major(n, 1, dev)
+                ws_solve = q.solve_workspace(1)
+                step()
+                t_solve = timed(lambda: q.solve(Qpost, R, Bpost, X, ws_solve))
+                x_direct = torch.linalg.solve(A, B)
+                out["solve"] = {"ms": round(t_solve, 4), "rel_err_vs_direct":
+                                (torch.linalg.norm(X - x_direct) / torch.linalg.norm(x_direct)).item()}
+                del X, ws_solve, x_direct
+            log(f"[{leg}] coded legs done")
+
+            # profiled pass: per-kernel HIP events on the library's streams
+            q.profile(True)
+            step()
+            torch.cuda.synchronize()
+            rep = q.profile_report()
+            q.profile(False)
+            phases = {k2: {"ms": round(r["ms"], 4), "launches": r["launches"],
+                           "avg_us": round(1e3 * r["ms"] / max(r["launches"], 1), 3),
+                           "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3),
+                           "gbs": round(r["bytes"] / max(r["ms"], 1e-9) / 1e6, 1)}
+                      for k2, r in rep.items() if r["launches"]}
+            L["phases"] = phases
+            L["overhead"]["T_recov_ms_per_event"] = round(rep["recover"]["ms"] / max(len(sched), 1), 4)
+            if li == 0:
+                out["roofline"] = roofline_of(rep, b, leg, args.workload)
         q.close()
-        cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead, precision=prec)
-        qu = cqr.CodedQR(cu, None, None, dev)
-        Au, Ru = qu.alloc()
 
-        def fac_u():
-            Au.copy_(A)
-            qu.factor(Au, Ru)
-        t_copy_u = timed(lambda: Au.copy_(A))
-        t_fu = timed(fac_u) - t_copy_u
-        floor = (1 + (mp - n) / n) * (1 + d / n) - 1
-        out["overhead"].update({
-            "T_factor_uncoded_ms": round(t_fu, 4),
-            "overhead_pct": round(100 * (t_enc + t_fac + t_post - t_fu) / t_fu, 2),
-            "floor_pct": round(100 * floor, 2),
-            "uncoded_tflops": round(model_flops(n, n, 0, b) / (t_fu * 1e-3) / 1e12, 4),
-            "useful_tflops": round(model_flops(n, n, 0, b) / (ms * 1e-3) / 1e12, 4),
-        })
-        qu.close()
-        log("uncoded leg done")
+        if not args.no_extras:
+            # uncoded: same library and precision, K = 0, with the coded plan
+            # released first (each plan's lookahead holds two streams; with both
+            # plans alive there are more streams than the device's four hardware
+            # queues, and the uncoded plan's streams could serialize)
+            cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead,
+                            precision=PRECISIONS[leg]["code"])
+            qu = cqr.CodedQR(cu, None, None, dev)
+            Au, Ru = qu.alloc()
+
+            def fac_u():
+                Au.copy_(A)
+                qu.factor(Au, Ru)
+            t_copy_u = timed(lambda: Au.copy_(A))
+            t_fu = timed(fac_u) - t_copy_u
+            ov = L["overhead"]
+            ov.update({"T_factor_uncoded_ms": round(t_fu, 4),
+                       "overhead_pct": round(100 * (ov["T_enc_ms"] + ov["T_factor_coded_ms"] + ov["T_post_ms"] - t_fu)
+                                             / t_fu, 2),
+                       "floor_pct": round(100 * floor, 2),
+                       "uncoded_tflops": round(model_flops(n, n, 0, b) / (t_fu * 1e-3) / 1e12, 4)})
+            qu.close()
+            del Au, Ru
+            torch.cuda.empty_cache()
+            log(f"[{leg}] uncoded leg done")
+        out["legs"][leg] = L
+
+    L0 = out["legs"][legs[0]]
+    out["value"] = L0["tflops"]
+    out["ms_per_step"] = L0["ms_per_step"]
+    out["errors"] = L0["errors"]
+    if "overhead" in L0:
+        out["overhead"] = L0["overhead"]
+    if len(legs) > 1:
+        out["mixed_vs_fp64"] = {
+            leg: {"speedup": round(L0["ms_per_step"] / out["legs"][leg]["ms_per_step"], 4),
+                  "orth_coded": out["legs"][leg]["errors"]["orth_coded"],
+                  "residual": out["legs"][leg]["errors"]["residual"]}
+            for leg in legs[1:]}
+    del first, At, R, Qpost, Bpost, A, B
+    torch.cuda.empty_cache()
 
     if args.calib_copy:
         # reference for rocprofv3 FETCH_SIZE / WRITE_SIZE: reads and writes exactly 512 MiB each
@@ -692,35 +704,134 @@ def main():
         del xs, ys
 
     if not args.no_cpu_baseline:
-        from oracle import coded_qr as oc
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
-        except Exception:
-            cores = os.cpu_count()
-        lay = oc.Layout(n, n, pr, pr, K, K, w["storage"])
-        prob = oc.Problem(A_host, lay, v, gh, oc.FactorOptions(b, "icgs"), sched, rhs_host)
-        reps = 2 if n >= 4096 else max(1, int(10.0 / max(1e-3, 1e-11 * F)))
-        if n > 8192:
-            out["cpu_baseline"] = None
-        else:
-            import contextlib
-            limit = contextlib.nullcontext()
-            if args.cpu_threads > 0:
-                from threadpoolctl import threadpool_limits
-                limit = threadpool_limits(limits=args.cpu_threads)
-                cores = args.cpu_threads
-            with limit:
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    oc.run(prob)
-                tc = (time.perf_counter() - t0) / reps
-            out["cpu_baseline"] = {"value": round(F / tc / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
-                                   "kind": "oracle",
-                                   "sample": f"{reps} full oracle step(s) of the same workload (encode, ICGS "
-                                             f"factor with the same failures, recovery, post-orth), "
-                                             f"{tc * 1e3:.1f} ms each"}
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_baseline(args, w, F)
+        log("cpu baseline done")
+    print(json.dumps(out), flush=True)
+
+
+PRECISIONS = {
+    "fp64": {"code": 0, "dtype": "f64", "desc": "FP64 throughout"},
+    "fp32": {"code": 1, "dtype": "f64 (R_bar on FP32 MFMA)",
+             "desc": "coefficient product R_bar = Qbar^T Q_t on FP32 MFMA (FP32 sums over 16 k-values, FP64 "
+                     "across them); rank-b update, re-projection, panels, decode, post-orth in FP64"},
+}
+
+
+def kernel_of(phase: str, b: int, leg: str) -> str:
+    """Kernel symbol behind a single-kernel phase (kernels are template-tagged per use)."""
+    k = KERNEL_OF[phase]
+    if phase == "trailing_update" and b >= 128:
+        k = "nnw16_kernel<0>"            # K = b >= 128: the 16-deep-slab form
+    if phase == "trailing_product" and b > 64:
+        # panels of several tile rows: two tile rows per workgroup (every
+        # trailing product of the n = 32768 workload has >= 4 tile columns)
+        k = "tn2_kernel<0, false>"
+    if phase == "trailing_product" and leg == "fp32":
+        k = k.replace("<0, false>", "<0, true>")
+    return k
+
+
+def roofline_of(rep: dict, b: int, leg: str, workload: str) -> dict:
+    """Roofline of the kernel holding the most time among phases that are exactly
+    one kernel symbol (so rocprofv3's per-kernel average describes the same
+    launches): algorithmic flops (or bytes) of its launches / their summed
+    HIP-event durations on the stream they ran on."""
+    dom = max((k for k in SINGLE_KERNEL_PHASES if rep[k]["launches"]), key=lambda k: rep[k]["ms"])
+    r = rep[dom]
+    f32_product = leg == "fp32" and dom == "trailing_product"
+    mfma_peak = PEAK["fp32_mfma_tflops" if f32_product else "fp64_mfma_tflops"]
+    # the rank-b update moves 16 bytes (read and write of C) per 2b flops:
+    # MFMA-bound when b/8 flop/B exceeds the ridge peak / HBM bandwidth
+    update_mfma = dom == "trailing_update" and b / 8.0 > mfma_peak * 1e3 / PEAK["hbm_gbs"]
+    if dom in MFMA_PHASES or update_mfma:
+        ach = r["flops"] / (r["ms"] * 1e-3) / 1e12
+        roof = {"kernel": kernel_of(dom, b, leg), "phase": dom, "bound": "mfma", "achieved": round(ach, 3),
+                "peak": mfma_peak, "unit": "TFLOP/s", "frac": round(ach / mfma_peak, 4)}
+    else:
+        ach = r["bytes"] / (r["ms"] * 1e-3) / 1e9
+        roof = {"kernel": kernel_of(dom, b, leg), "phase": dom, "bound": "hbm", "achieved": round(ach, 1),
+                "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
+    roof["avg_launch_us"] = round(1e3 * r["ms"] / r["launches"], 3)
+    roof["launches"] = r["launches"]
+    roof["flops_per_launch"] = r["flops"] / r["launches"]
+    roof["share_of_profiled_step"] = round(r["ms"] / sum(x["ms"] for x in rep.values()), 3)
+    roof["traffic"] = traffic_record(dom, workload) if leg == "fp64" else None
+    roof["events_per_step"] = 2 * sum(x["launches"] for x in rep.values())
+    return roof
+
+
+def cpu_baseline(args, w: dict, F_workload: float) -> dict:
+    """The FP64 oracle (plain numpy, unchanged) on the host cores, on a bounded
+    sample: the full oracle step (encode, ICGS factor with the workload's kind
+    of failures, recovery, post-orth) of the same workload, or, for workloads
+    the host cannot finish in about half a minute, of the same grid, code and
+    failure pattern at a reduced n (same block count and panel width, smaller
+    blocks).  Its rate in the metric's unit is model flops / time."""
+    import contextlib
+    import platform
+    import subprocess
+    from oracle import coded_qr as oc
+    n, pr, K, b = w["n"], w["pr"], w["K"], w["b"]
+    n_s = n if n <= 4096 else max(16 * pr, min(n, w.get("cpu_sample_n", 4096)))
+    inp = workload_inputs_at(w, n_s, args.seed)
+    lay = oc.Layout(n_s, n_s, pr, pr, K, K, w["storage"])
+    prob = oc.Problem(inp["A"], lay, inp["v"], inp["gh"], oc.FactorOptions(b, "icgs"), inp["schedule"], inp["rhs"])
+    F_s = model_flops(lay.mp, n_s, lay.N - n_s, b)
+    limit = contextlib.nullcontext()
+    blas = {}
+    cores = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            cores = max(i.get("num_threads", 1) for i in info)
+            blas = {"library": info[0].get("internal_api"), "version": info[0].get("version"),
+                    "threading": info[0].get("threading_layer")}
+        if args.cpu_threads > 0:
+            limit = threadpool_limits(limits=args.cpu_threads)
+            cores = args.cpu_threads
+    except Exception:
+        pass
+    model = platform.processor() or ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    reps = 1 if n_s >= 4096 else max(1, int(10.0 / max(1e-3, 1e-11 * F_s)))
+    with limit:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oc.run(prob)
+        tc = (time.perf_counter() - t0) / reps
+    rate = F_s / tc / 1e12
+    sample = (f"{reps} full oracle step(s) (encode, ICGS factor with the workload's failure pattern, recovery, "
+              f"post-orth) at n={n_s} on the workload's {pr}x{pr} grid, b={b}, K={K} {w['storage']}-node, "
+              f"{tc:.2f} s each")
+    res = {"value": round(rate, 5), "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": sample,
+           "cpu_model": model, "blas": blas, "host_cpus": os.cpu_count()}
+    if n_s != n:
+        res["extrapolated_step_s"] = round(F_workload / (rate * 1e12), 1)
+        res["extrapolation"] = "the workload's step time at this rate (model flops / rate); labelled extrapolated"
+    return res
+
+
+def workload_inputs_at(w: dict, n: int, seed: int) -> dict:
+    """workload_inputs for the workload's grid, code and failure pattern at
+    another n (the oracle's bounded CPU sample)."""
+    pr, K, b = w["pr"], w["K"], w["b"]
+    # the failure tolerance of the workload's code (in-node: the largest f with
+    # f + f ceil(f / (p_r - f)) <= K)
+    ftol = K if w["storage"] == "out" else max(
+        f for f in range(1, pr) if f + f * (-(-f // (pr - f))) <= K)
+    return {
+        "A": synth.gaussian(n, n, seed),
+        "rhs": synth.gaussian(n, 1, seed + 1),
+        "v": synth.q_generator_draws(K, pr, seed),
+        "gh": synth.r_generator_draws(pr, K, seed),
+        "schedule": synth.draw_schedule(w["kind"], n // b, pr, pr, seed, nfail=w["nfail"], every=16, f=ftol),
+    }
 
 
 if __name__ == "__main__":
