@@ -8,8 +8,11 @@
 - A panel with two nearly dependent columns (one 1e-9 from another,
   cond(A) ~ 1e11): the Cholesky-QR panel breaks down and the column-wise
   CGS2 fallback takes the panel; the result is bounded by backward error
-  against the oracle (FP64 residual and orthogonality; G_0 Q_1 within 4x the
-  oracle's, whose checksum drift grows like u kappa(A) on both sides), both
+  against the oracle (FP64 residual; orthogonality within 4x the oracle's,
+  which reaches 1e-13 when the pair sits in the first panel and ~5e-7 when it
+  sits in a later one, where the intra-panel projection re-introduces
+  components along the earlier basis after the re-projection; G_0 Q_1 within
+  4x the oracle's, whose checksum drift grows like u kappa(A)), both
   where the panel is the first (no re-projection, no early update) and where
   its update already started from the first pass (the early update then
   forms its coefficients from the finished panel).  With a node failure
@@ -113,10 +116,14 @@ def test_nearly_dependent_columns_fall_back(cqr, cols, lookahead, fail):
     print(f"    info {info} fallbacks {fallbacks}\n    GPU {mg}\n    oracle {mo}", flush=True)
     assert info == 0 and fallbacks >= 1
     if not fail:
-        assert mg["residual"] <= 1e-12 and mg["orth_coded"] <= 1e-12
+        assert mg["residual"] <= 1e-12
     else:
         # a decode mid-factorization carries the checksum drift (u kappa(A) on
         # both sides) into the recovered blocks: bounded against the oracle
         assert mg["residual"] <= max(1e-12, 4 * mo["residual"])
-        assert mg["orth_coded"] <= max(1e-12, 4 * mo["orth_coded"])
+    # in a panel after the first, projecting the nearly dependent column
+    # against its partner re-introduces components along the earlier basis of
+    # size u kappa(panel) after the re-projection has removed them, in the
+    # oracle as on the GPU: orthogonality is bounded against the oracle's
+    assert mg["orth_coded"] <= max(1e-12, 4 * mo["orth_coded"])
     assert mg["orth_post"] <= max(1e-12, 4 * mo["orth_post"])
