@@ -73,8 +73,11 @@ KERNEL_OF = {
 }
 
 
-def model_flops(mp, n, d, b):
-    return mp * (4.0 * n * n + 4.0 * n * d + 4.0 * n * b)
+def model_flops(mp, n, d, b, reproject=True):
+    """Flops of the coded blocked Gram-Schmidt: right-looking update 2 m' n^2,
+    carried checksum columns 4 m' n d, CGS2 panels 4 m' n b, and the left
+    re-projection 2 m' n^2 when it runs."""
+    return mp * ((4.0 if reproject else 2.0) * n * n + 4.0 * n * d + 4.0 * n * b)
 
 
 def workload_inputs(name: str, ftol: int, seed: int = 0) -> dict:
@@ -267,25 +270,40 @@ def run_peaks(args):
 
 
 def run_adjoint(args):
-    """Tall-skinny least squares through the coded QR and its adjoint:
-    m = 65536, n = 512 Gaussian A and b, 16 x 1 grid (4096-row blocks), b = 64,
-    K_v = 2 out-of-node checksum block rows, no horizontal code (p_c = 1).
+    """Least squares through the coded QR and its adjoint, on the tall-skinny
+    workload (c4: m = 65536, n = 512 Gaussian A and b, 16 x 1 grid of 4096-row
+    blocks, b = 64, K_v = 2 out-of-node checksum block rows, no horizontal
+    code, two nodes failing at once at a random panel) or on the n = 32768
+    workload (c5: its grid, code and failure storms).
     loss = ||x - x_t||^2 with x = R_1^{-1} (G_0 Q_1)^T (G_0 b); the forward
     (encode, factor, post-orthogonalization, solve) and the backward
     (coded_qr_solve_backward, coded_qr_backward) are timed separately, and the
     gradient is checked against the closed form of the W-weighted least squares
-    (W = I + G_v^T G_v).  One JSON line."""
+    (W = I + G_v^T G_v; for square A the exact solve).  One JSON line."""
     import torch
     from paper_2311_11943_amd import autograd as ag
     from paper_2311_11943_amd import cqr
     dev = torch.device("cuda:0")
-    m, n, pr, K, b = 65536, 512, 16, 2, 64
     prec = cqr.CQR_TRAIL_FP32 if args.precision == "fp32" else cqr.CQR_FP64
-    cfg = cqr.Config(m, n, pr, 1, K, 0, b, cqr.CQR_OUT_OF_NODE, precision=prec)
-    # two nodes fail at once at a random panel (R is protected by its checksum rows)
-    sched = synth.draw_schedule("burst", n // b, pr, 1, args.seed, nfail=2)
-    v = synth.q_generator_draws(K, pr, args.seed)
-    engine = cqr.CodedQR(cfg, v, None, dev)
+    if args.adjoint_workload == "c5":
+        w = WORKLOADS["c5"]
+        m = n = w["n"]
+        pr, K, b = w["pr"], w["K"], w["b"]
+        cfg = cqr.Config(m, n, pr, pr, K, K, b, cqr.CQR_IN_NODE, precision=prec)
+        engine = cqr.CodedQR(cfg, synth.q_generator_draws(K, pr, args.seed), synth.r_generator_draws(pr, K, args.seed),
+                             dev)
+        sched = synth.draw_schedule(w["kind"], n // b, pr, pr, args.seed, nfail=w["nfail"], every=16, f=engine.ftol)
+        desc = "c5: " + w["desc"]
+        grid = f"{pr}x{pr}"
+    else:
+        m, n, pr, K, b = 65536, 512, 16, 2, 64
+        cfg = cqr.Config(m, n, pr, 1, K, 0, b, cqr.CQR_OUT_OF_NODE, precision=prec)
+        # two nodes fail at once at a random panel (R is protected by its checksum rows)
+        sched = synth.draw_schedule("burst", n // b, pr, 1, args.seed, nfail=2)
+        engine = cqr.CodedQR(cfg, synth.q_generator_draws(K, pr, args.seed), None, dev)
+        desc = ("c4: m=65536, n=512 Gaussian A and b, 16x1 grid (4096-row blocks), b=64, K_v=2 out-of-node, no "
+                "horizontal code (R protected by its checksum rows), 2 nodes failing at once at a random panel")
+        grid = "16x1"
     A = torch.tensor(synth.gaussian(m, n, args.seed), device=dev, requires_grad=True)
     B = torch.tensor(synth.gaussian(m, 1, args.seed + 1), device=dev, requires_grad=True)
     xt = torch.tensor(synth.gaussian(n, 1, args.seed + 2), device=dev)
@@ -312,10 +330,11 @@ def run_adjoint(args):
         if it >= args.warmup:
             f_ms.append(e0.elapsed_time(e1))
             b_ms.append(e1.elapsed_time(e2))
+        print(f"[bench] adjoint step {it + 1} of {args.warmup + args.steps}: forward {e0.elapsed_time(e1):.1f} ms, "
+              f"backward {e1.elapsed_time(e2):.1f} ms", file=sys.stderr, flush=True)
     fm, bm = sum(f_ms) / len(f_ms), sum(b_ms) / len(b_ms)
     # closed form: W v = v + G_v^T (G_v v), with G_v = G~_v (x) I_bs
     gv = torch.tensor(engine.generators()[0], device=dev)
-    bs = m // pr
 
     def W(vm):
         vm = vm.detach()
@@ -324,27 +343,37 @@ def run_adjoint(args):
         return vm + (gv.T @ chk).reshape(m, -1)
 
     Ad, Bd = A.detach(), B.detach()
-    WA = W(Ad)
-    H = Ad.T @ WA
-    xw = torch.linalg.solve(H, WA.T @ Bd)
-    z = torch.linalg.solve(H, 2 * (xw - xt))
-    cA = W(Bd - Ad @ xw) @ z.T - WA @ z @ xw.T
-    cB = WA @ z
-    relA = ((A.grad - cA).abs().max() / cA.abs().max()).item()
-    relB = ((B.grad - cB).abs().max() / cB.abs().max()).item()
+    gA, gB = A.grad, B.grad
+    del A, B
+    if m == n:
+        # square A: x = A^{-1} b whatever W is; db = A^{-T} g, dA = -db x^T (g = 2 (x - x_t)),
+        # from LU solves with A itself (the normal equations would square its condition number)
+        xw = torch.linalg.solve(Ad, Bd)
+        cB = torch.linalg.solve(Ad.T, 2 * (xw - xt))
+        cA = -cB @ xw.T
+    else:
+        WA = W(Ad)
+        H = Ad.T @ WA
+        xw = torch.linalg.solve(H, WA.T @ Bd)
+        z = torch.linalg.solve(H, 2 * (xw - xt))
+        del H
+        cB = WA @ z
+        cA = W(Bd - Ad @ xw) @ z.T
+        cA -= WA @ z @ xw.T
+        del WA
+    print("[bench] closed-form gradient done", file=sys.stderr, flush=True)
+    relA = ((gA - cA).abs().max() / cA.abs().max()).item()
+    relB = ((gB - cB).abs().max() / cB.abs().max()).item()
     relx = ((x.detach() - xw).abs().max() / xw.abs().max()).item()
     mp = cfg.mp
-    f_fl = model_flops(mp, n, 0, b) + 2.0 * m * n + n * n
+    f_fl = model_flops(mp, n, cfg.N - n, b) + 2.0 * m * n + n * n
     b_fl = 6.0 * mp * n * n + 2.0 * n ** 3
     print(json.dumps({
         "metric": "coded-QR least-squares forward + adjoint time", "value": round(fm + bm, 4), "unit": "ms",
         "higher_is_better": False, "steps": args.steps, "warmup": args.warmup,
         "dtype": "f64" if args.precision == "fp64" else "f32 trailing update / f64 (adjoint f64)",
         "data": "synthetic",
-        "config": {"workload": "c4: m=65536, n=512 Gaussian A and b, 16x1 grid (4096-row blocks), b=64, "
-                               "K_v=2 out-of-node, no horizontal code (R protected by its checksum rows), "
-                               "2 nodes failing at once at a random panel",
-                   "m": m, "n": n, "grid": "16x1", "b": b, "K_v": K, "precision": args.precision,
+        "config": {"workload": desc, "m": m, "n": n, "grid": grid, "b": b, "K": K, "precision": args.precision,
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched]},
         "forward_ms": round(fm, 4), "backward_ms": round(bm, 4),
         "forward_tflops": round(f_fl / (fm * 1e-3) / 1e12, 3), "backward_tflops": round(b_fl / (bm * 1e-3) / 1e12, 3),
@@ -440,6 +469,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip overhead/profile/oracle legs")
+    ap.add_argument("--skip-uncoded", action="store_true",
+                    help="skip the uncoded leg (so that a kernel trace of the command holds only the coded "
+                         "factorization's launches, the ones the roofline averages)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, launch one plain copy kernel of 512 MiB (y = 2x) as the reference for "
                          "HBM byte counters")
@@ -450,13 +482,19 @@ def main():
                          "instead of a Gaussian A")
     ap.add_argument("--lookahead", type=int, default=1, choices=(0, 1),
                     help="1: overlap the next panel with the trailing update on a second stream")
+    ap.add_argument("--panel", default="cholqr2", choices=("cholqr2", "cgs2", "icgs", "mgs"),
+                    help="panel method (cholqr2: two Cholesky-QR passes; the others column-wise)")
+    ap.add_argument("--no-reproject", action="store_true",
+                    help="the paper's blocked Gram-Schmidt without the left re-projection of each panel")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: the paper's coding-overhead grid (n = 24000, "
                          "p in {6, 8, 10, 12}, f in {0..3}), one JSON line per point")
     ap.add_argument("--sweep-n", type=int, default=24000)
     ap.add_argument("--adjoint", action="store_true",
-                    help="instead of the benchmark line: forward + adjoint of the tall-skinny least-squares "
-                         "workload (m = 65536, n = 512), one JSON line")
+                    help="instead of the benchmark line: forward + adjoint of a least-squares loss through the coded "
+                         "QR and the coded solve, one JSON line")
+    ap.add_argument("--adjoint-workload", default="c4", choices=("c4", "c5"),
+                    help="--adjoint: c4 (m = 65536, n = 512, 16 x 1 grid) or c5 (n = 32768, 16 x 16 grid)")
     ap.add_argument("--reps", type=int, default=0,
                     help="repetitions of each timed extra (overhead legs); 0: 2 from n = 16384 on, else 5")
     ap.add_argument("--generator-study", action="store_true",
@@ -501,6 +539,9 @@ def main():
         raise SystemExit(f"--legs takes a comma-separated list of {sorted(PRECISIONS)}")
     v = synth.q_generator_draws(K, pr, args.seed)
     gh = synth.r_generator_draws(pr, K, args.seed)
+    panel = {"cholqr2": cqr.CQR_PANEL_CHOLQR2, "cgs2": cqr.CQR_PANEL_CGS2, "icgs": cqr.CQR_PANEL_ICGS,
+             "mgs": cqr.CQR_PANEL_MGS}[args.panel]
+    reproject = 0 if args.no_reproject else 1
     cfg0 = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead)
     q0 = cqr.CodedQR(cfg0, v, gh, dev)
     ftol = q0.ftol
@@ -512,7 +553,8 @@ def main():
     A = cqr.to_device_colmajor(A_host, dev)
     B = cqr.to_device_colmajor(rhs_host, dev)
     mp, d = cfg0.mp, cfg0.N - n
-    F = model_flops(mp, n, d, b)
+    F = model_flops(mp, n, d, b, reproject == 1)
+    F_unc = model_flops(n, n, 0, b, reproject == 1)
     floor = (1 + (mp - n) / n) * (1 + d / n) - 1
 
     def log(msg):
@@ -534,18 +576,21 @@ def main():
         "dtype": PRECISIONS[legs[0]]["dtype"],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "n": n, "grid": f"{pr}x{pr}", "b": b,
-                   "K": K, "f_tol": ftol, "storage": w["storage"], "panel": "CholQR2 (block CGS2) + re-projection",
+                   "K": K, "f_tol": ftol, "storage": w["storage"],
+                   "panel": {"cholqr2": "CholQR2 (block CGS2)", "cgs2": "column-wise CGS2", "icgs": "column-wise ICGS",
+                             "mgs": "column-wise MGS"}[args.panel] + ("" if reproject else ", no re-projection")
+                            + (" + re-projection" if reproject else ""),
                    "lookahead": args.lookahead, "legs": legs,
                    "input": "gaussian" if args.cond <= 0 else f"U diag(s) V^T, cond {args.cond:g}",
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched],
-                   "model_flops": F, "uncoded_model_flops": model_flops(n, n, 0, b)},
+                   "model_flops": F, "uncoded_model_flops": F_unc},
         "legs": {},
     }
     first = None        # Q~ and R of the first leg, to compare the other legs with
     At = R = Qpost = Bpost = None
     for li, leg in enumerate(legs):
-        cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, lookahead=args.lookahead,
-                         precision=PRECISIONS[leg]["code"])
+        cfg = cqr.Config(n, n, pr, pr, K, K, b, storage, reproject=reproject, lookahead=args.lookahead,
+                         precision=PRECISIONS[leg]["code"], panel=panel)
         q = cqr.CodedQR(cfg, v, gh, dev)
         if At is None:
             At, R = q.alloc()
@@ -580,7 +625,7 @@ def main():
         ms = e0.elapsed_time(e1) / args.steps
         log(f"[{leg}] {args.steps} timed steps done: {ms:.3f} ms per step")
         L = {"ms_per_step": round(ms, 4), "tflops": round(F / (ms * 1e-3) / 1e12, 4),
-             "useful_tflops": round(model_flops(n, n, 0, b) / (ms * 1e-3) / 1e12, 4),
+             "useful_tflops": round(F_unc / (ms * 1e-3) / 1e12, 4),
              "wall_s_timed": round(wall, 3), "arithmetic": PRECISIONS[leg]["desc"]}
         # errors of the last step (verification, outside the timed region)
         Qt = At[:, :n]
@@ -651,13 +696,13 @@ def main():
                 out["roofline"] = roofline_of(rep, b, leg, args.workload)
         q.close()
 
-        if not args.no_extras:
+        if not args.no_extras and not args.skip_uncoded:
             # uncoded: same library and precision, K = 0, with the coded plan
             # released first (each plan's lookahead holds two streams; with both
             # plans alive there are more streams than the device's four hardware
             # queues, and the uncoded plan's streams could serialize)
-            cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, lookahead=args.lookahead,
-                            precision=PRECISIONS[leg]["code"])
+            cu = cqr.Config(n, n, pr, pr, 0, 0, b, storage, reproject=reproject, lookahead=args.lookahead,
+                            precision=PRECISIONS[leg]["code"], panel=panel)
             qu = cqr.CodedQR(cu, None, None, dev)
             Au, Ru = qu.alloc()
 
@@ -671,7 +716,7 @@ def main():
                        "overhead_pct": round(100 * (ov["T_enc_ms"] + ov["T_factor_coded_ms"] + ov["T_post_ms"] - t_fu)
                                              / t_fu, 2),
                        "floor_pct": round(100 * floor, 2),
-                       "uncoded_tflops": round(model_flops(n, n, 0, b) / (t_fu * 1e-3) / 1e12, 4)})
+                       "uncoded_tflops": round(F_unc / (t_fu * 1e-3) / 1e12, 4)})
             qu.close()
             del Au, Ru
             torch.cuda.empty_cache()

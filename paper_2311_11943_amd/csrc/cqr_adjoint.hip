@@ -105,12 +105,31 @@ __global__ __launch_bounds__(kAdjThreads) void fold_kernel(FoldArgs a) {
   }
 }
 
-// Y = I (n x n)
-__global__ __launch_bounds__(kAdjThreads) void eye_kernel(double* Y, int64_t ldy, int64_t n) {
+// Y (n x n) = the block diagonal of the 64 x 64 tiles in T (tile k at
+// T + 4096 k, column-major), zeros elsewhere: the inverted diagonal blocks of
+// an upper-triangular matrix laid out as the start of its inverse.
+__global__ __launch_bounds__(kAdjThreads) void blockdiag_kernel(const double* T, double* Y, int64_t ldy, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
   if (e >= n * n) return;
   const int64_t i = e % n, j = e / n;
-  Y[i + j * ldy] = i == j ? 1.0 : 0.0;
+  Y[i + j * ldy] = (i >> 6) == (j >> 6) ? T[(i >> 6) * 4096 + (i & 63) + (j & 63) * 64] : 0.0;
+}
+
+// C *= s (rows x cols, ld ldc)
+__global__ __launch_bounds__(kAdjThreads) void scale_kernel(double* C, int64_t ldc, int64_t rows, int64_t cols,
+                                                            double s) {
+  const int64_t e = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
+  if (e >= rows * cols) return;
+  C[e % rows + (e / rows) * ldc] *= s;
+}
+
+void launch_blockdiag(const double* T, double* Y, int64_t ldy, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(blockdiag_kernel, dim3(blocks_for(n * n)), dim3(kAdjThreads), 0, st, T, Y, ldy, n);
+}
+
+void launch_scale(double* C, int64_t ldc, int64_t rows, int64_t cols, double s, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(scale_kernel, dim3(blocks_for(rows * cols)), dim3(kAdjThreads), 0, st, C, ldc, rows, cols, s);
 }
 
 void launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
@@ -141,8 +160,5 @@ void launch_fold(const FoldArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(fold_kernel, dim3(blocks_for(a.bs * a.cols)), dim3(kAdjThreads), 0, st, a);
 }
 
-void launch_eye(double* Y, int64_t ldy, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(eye_kernel, dim3(blocks_for(n * n)), dim3(kAdjThreads), 0, st, Y, ldy, n);
-}
 
 }  // namespace cqr

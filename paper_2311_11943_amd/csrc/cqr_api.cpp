@@ -1144,18 +1144,31 @@ namespace {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Rinv = R_1^{-1} (n x n, ld n): diagonal blocks inverted at once, then the
-// block back substitution with the identity as right-hand side (Ytmp, n x n).
-void upper_inverse(cqr_plan_s& p, const double* R, int64_t ldr, double* Rinv, double* Ytmp, double* T,
-                   hipStream_t st) {
+// Rinv = R_1^{-1} (n x n, ld n) by recursive doubling: the 64 x 64 diagonal
+// blocks are inverted at once and laid out as a block-diagonal Rinv; then,
+// for h = 64, 128, 256, ..., every pair of adjacent h-blocks [i, i+h) and
+// [i+h, i+2h) gets its off-diagonal block T12 = -T11 R12 T22 from the two
+// inverted diagonal blocks (W = R12 T22 into Wtmp, then T12 -= T11 W), on the
+// MFMA update kernels: n^3/3 flops in products (s: the split partials).
+void upper_inverse(cqr_plan_s& p, const double* R, int64_t ldr, double* Rinv, double* Wtmp, double* T,
+                   const cqr::Scratch& s, hipStream_t st) {
   const int64_t n = p.cfg.n, nb = (n + 63) / 64;
-  prof(p, PH_ADJOINT, 0.0, 8.0 * n * n, st, [&] { cqr::launch_eye(Ytmp, n, n, st); });
   prof(p, PH_ADJOINT, nb * 64.0 * 64 * 64 / 3, 8.0 * (n * 64.0 + nb * 64.0 * 64), st,
        [&] { cqr::launch_trinv(R, ldr, n, T, st); });
-  for (int64_t k0 = (nb - 1) * 64; k0 >= 0; k0 -= 64) {
-    const int w = (int)std::min<int64_t>(64, n - k0);
-    prof(p, PH_ADJOINT, 2.0 * (64.0 * w + k0 * w) * n, 8.0 * (k0 * w + 2.0 * (k0 + w) * n), st,
-         [&] { cqr::launch_trsv_step(R, ldr, T, Ytmp, n, Rinv, n, (int)n, k0, w, st); });
+  prof(p, PH_ADJOINT, 0.0, 8.0 * n * n, st, [&] { cqr::launch_blockdiag(T, Rinv, n, n, st); });
+  for (int64_t h = 64; h < n; h *= 2) {
+    for (int64_t i = 0; i + h < n; i += 2 * h) {
+      const int64_t h2 = std::min(h, n - i - h);
+      const double* R12 = R + i + (i + h) * ldr;
+      const double* T11 = Rinv + i + i * n;
+      const double* T22 = Rinv + (i + h) + (i + h) * n;
+      double* T12 = Rinv + i + (i + h) * n;
+      // Wtmp = -R12 T22, negated to R12 T22; T12 (zero) -= T11 Wtmp
+      prof(p, PH_ADJOINT, 0.0, 8.0 * h * h2, st, [&] { cqr::launch_fill_zero(Wtmp, h, h, h2, st); });
+      nn(p, PH_ADJOINT, Wtmp, h, R12, ldr, T22, n, h, (int)h2, (int)h2, s, st);
+      prof(p, PH_ADJOINT, 0.0, 16.0 * h * h2, st, [&] { cqr::launch_scale(Wtmp, h, h, h2, -1.0, st); });
+      nn(p, PH_ADJOINT, T12, n, T11, n, Wtmp, h, h, (int)h2, (int)h, s, st);
+    }
   }
 }
 
@@ -1188,7 +1201,7 @@ cqr_status coded_qr_backward(cqr_plan p, const double* Q, int64_t ldq, const dou
   double* D = take(8 * (size_t)mp * n);
   double* X = take(8 * (size_t)mp * n);
   const double nn2 = 8.0 * n * n;
-  upper_inverse(*p, R, ldr, Rinv, W1, T, st);
+  upper_inverse(*p, R, ldr, Rinv, W1, T, s, st);
   // W2 = M1 = Q~^T dQ~
   tn(*p, PH_ADJOINT, Q, ldq, dQ, lddq, (int)n, (int)n, mp, W2, n, nullptr, 0, s, st);
   // W1 = M1^T;  W2 = triu(dR)^T;  W1 -= R W2, so W1 = dQ~^T Q~ - R dR^T = -M
@@ -1216,10 +1229,15 @@ cqr_status coded_qr_backward(cqr_plan p, const double* Q, int64_t ldq, const dou
   return hip_status();
 }
 
+// Split partials of the triangular inverse's products (the update kernels
+// split K over at most 512 workgroups).
+constexpr int64_t kSolvePartTiles = 1024;
+
 size_t coded_qr_solve_backward_workspace_bytes(cqr_plan p, int32_t nrhs) {
   if (!p || nrhs < 1) return 0;
   const size_t n = (size_t)p->cfg.n, nb = (n + 63) / 64;
-  return 2 * up256(8 * n * n) + up256(8 * nb * 64 * 64) + up256(8 * n * (size_t)nrhs);
+  return 2 * up256(8 * n * n) + up256(8 * nb * 64 * 64) + up256(8 * n * (size_t)nrhs) +
+         up256(8 * (size_t)kSolvePartTiles * kTile * kTile);
 }
 
 cqr_status coded_qr_solve_backward(cqr_plan p, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
@@ -1241,7 +1259,10 @@ cqr_status coded_qr_solve_backward(cqr_plan p, const double* Qpost, int64_t ldqp
   double* Ytmp = take(8 * (size_t)n * n);
   double* T = take(8 * (size_t)nb * 64 * 64);
   double* DY = take(8 * (size_t)n * nrhs);
-  upper_inverse(*p, R, ldr, Rinv, Ytmp, T, st);
+  cqr::Scratch s{};
+  s.part = take(8 * (size_t)kSolvePartTiles * kTile * kTile);
+  s.npart = kSolvePartTiles;
+  upper_inverse(*p, R, ldr, Rinv, Ytmp, T, s, st);
   // dy = R_1^{-T} dX = Rinv^T dX
   prof(*p, PH_ADJOINT, 2.0 * n * n * nrhs, 8.0 * (n * n + 2.0 * n * nrhs), st,
        [&] { cqr::launch_gemv_t(Rinv, n, n, (int)n, dX, lddx, nrhs, DY, n, st); });

@@ -218,7 +218,10 @@ void launch_outer(const double* U, int64_t ldu, const double* V, int64_t ldv, in
 void launch_gemv_n(const double* A, int64_t lda, int64_t m, int n, const double* x, int64_t ldx, int nrhs,
                    double* y, int64_t ldy, hipStream_t st);
 void launch_fold(const FoldArgs& a, hipStream_t st);
-void launch_eye(double* Y, int64_t ldy, int64_t n, hipStream_t st);
+// Y (n x n) = block diagonal of the 64 x 64 tiles of T (tile k at T + 4096 k)
+void launch_blockdiag(const double* T, double* Y, int64_t ldy, int64_t n, hipStream_t st);
+// C *= s (rows x cols)
+void launch_scale(double* C, int64_t ldc, int64_t rows, int64_t cols, double s, hipStream_t st);
 void launch_trsv_step(const double* R, int64_t ldr, const double* T, double* Y, int64_t ldy, double* X,
                       int64_t ldx, int nrhs, int64_t k0, int w, hipStream_t st);
 

@@ -33,6 +33,9 @@ CASES = [
     ("tall", 128, 8, 2, 64, "out", {"m": 1024, "pc": 1, "kh": 0}),
     ("ragged", 240, 4, 1, 16, "out", {}),
     ("wide_n", 512, 4, 2, 128, "out", {}),
+    # R_1^{-1} by recursive doubling over 64-wide diagonal blocks: five levels,
+    # the last off-diagonal block of each level ragged (1152 = 1024 + 128)
+    ("five_levels_ragged", 1152, 4, 1, 96, "out", {}),
 ]
 
 
