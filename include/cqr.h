@@ -270,6 +270,24 @@ cqr_status coded_qr_solve(cqr_plan plan, const double* Qpost, int64_t ldqp, cons
                           size_t ws_bytes, hipStream_t stream);
 
 /*
+ * coded_qr_solve without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops that
+ * forbid allocation).  Same arguments, kernels and result as coded_qr_solve
+ * (X bit-identical); its scratch (the inverted diagonal blocks of R_1 and
+ * Y = Qpost^T Bpost) is a file-scope device array of
+ * CQR_SOLVE_NOALLOC_MAX_BYTES, one copy per device, held until the process
+ * ends.  Returns CQR_ENOMEM, enqueueing nothing, when
+ * coded_qr_solve_workspace_bytes(plan, nrhs) exceeds that size.  Allocates
+ * nothing.  Every call on one device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.
+ */
+#define CQR_SOLVE_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+cqr_status coded_qr_solve_noalloc(cqr_plan plan, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
+                                  const double* Bpost, int64_t ldbp, int32_t nrhs, double* X, int64_t ldx,
+                                  hipStream_t stream);
+
+/*
  * Adjoint (reverse-mode derivative) of the coded QR.  Not in the paper: a
  * growth direction built on its definitions.  The coded QR maps A to the
  * factors of the encoded systematic columns, A~ = [A; G_v A] = Q~ R_1 (System

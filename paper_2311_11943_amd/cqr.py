@@ -26,7 +26,7 @@ EXPORTS = [
     "coded_qr_workspace_bytes", "coded_qr_encode", "coded_qr_factor", "coded_qr_ws_info",
     "coded_qr_erase", "coded_qr_recover", "coded_qr_postorth", "coded_qr_status_string",
     "coded_qr_profile_enable", "coded_qr_profile_read", "coded_qr_hip_error_name", "coded_qr_solve",
-    "coded_qr_solve_workspace_bytes", "coded_qr_backward", "coded_qr_backward_workspace_bytes",
+    "coded_qr_solve_workspace_bytes", "coded_qr_solve_noalloc", "coded_qr_backward", "coded_qr_backward_workspace_bytes",
     "coded_qr_solve_backward", "coded_qr_solve_backward_workspace_bytes", "coded_qr_plan_r_rows",
     "coded_qr_plan_placement", "coded_qr_ws_panel_fallbacks",
 ]
@@ -78,6 +78,7 @@ def _load() -> ctypes.CDLL:
         "coded_qr_postorth": (I32, [P, D, I64, D, I64, D, I64, D, I64, I32, V]),
         "coded_qr_solve": (I32, [P, D, I64, D, I64, D, I64, I32, D, I64, V, ctypes.c_size_t, V]),
         "coded_qr_solve_workspace_bytes": (ctypes.c_size_t, [P, I32]),
+        "coded_qr_solve_noalloc": (I32, [P, D, I64, D, I64, D, I64, I32, D, I64, V]),
         "coded_qr_backward_workspace_bytes": (ctypes.c_size_t, [P]),
         "coded_qr_plan_r_rows": (I64, [P]),
         "coded_qr_backward": (I32, [P, D, I64, D, I64, D, I64, D, I64, D, I64, V, ctypes.c_size_t, V]),
@@ -295,6 +296,17 @@ def coded_qr_solve(plan: int, Qpost, R, Bpost, X, ws, stream=None) -> int:
     return LIB.coded_qr_solve(ctypes.c_void_p(plan), _ptr(Qpost), _ld(Qpost), _ptr(R), _ld(R), _ptr(Bpost),
                               _ld(Bpost), Bpost.shape[1], _ptr(X), _ld(X), _ptr(ws),
                               ws.numel() * ws.element_size(), ctypes.c_void_p(_stream(stream)))
+
+
+# size of coded_qr_solve_noalloc's per-device scratch array
+CQR_SOLVE_NOALLOC_MAX_BYTES = 32 << 20
+
+
+def coded_qr_solve_noalloc(plan: int, Qpost, R, Bpost, X, stream=None) -> int:
+    """coded_qr_solve with the library's per-device scratch array instead of a
+    workspace (allocates nothing; overlapping calls on one device race)."""
+    return LIB.coded_qr_solve_noalloc(ctypes.c_void_p(plan), _ptr(Qpost), _ld(Qpost), _ptr(R), _ld(R), _ptr(Bpost),
+                                      _ld(Bpost), Bpost.shape[1], _ptr(X), _ld(X), ctypes.c_void_p(_stream(stream)))
 
 
 def coded_qr_plan_r_rows(plan: int) -> int:

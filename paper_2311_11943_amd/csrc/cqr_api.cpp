@@ -54,6 +54,7 @@ enum Phase { PH_ENCODE = 0, PH_REPROJ_TN, PH_REPROJ_NN, PH_GRAM, PH_CHOL, PH_APP
              PH_TRAIL_NN, PH_REDUCE, PH_RECOVER, PH_POST, PH_ERASE, PH_OTHER, PH_COLPANEL, PH_SOLVE,
              PH_ADJOINT };
 static_assert(PH_ADJOINT + 1 == CQR_NPHASES, "phase list and header disagree");
+static_assert(cqr::kSolveScratchBytes == CQR_SOLVE_NOALLOC_MAX_BYTES, "scratch size and header disagree");
 
 namespace {
 
@@ -1136,6 +1137,18 @@ cqr_status coded_qr_solve(cqr_plan p, const double* Qpost, int64_t ldqp, const d
          [&] { cqr::launch_trsv_step(R, ldr, T, Y, n, X, ldx, nrhs, k0, w, st); });
   }
   return hip_status();
+}
+
+cqr_status coded_qr_solve_noalloc(cqr_plan p, const double* Qpost, int64_t ldqp, const double* R, int64_t ldr,
+                                  const double* Bpost, int64_t ldbp, int32_t nrhs, double* X, int64_t ldx,
+                                  hipStream_t st) {
+  drop_pending_error();
+  if (!p || !Qpost || !R || !Bpost || !X || nrhs < 1) return CQR_EINVAL;
+  const size_t need = coded_qr_solve_workspace_bytes(p, nrhs);
+  if (need > cqr::kSolveScratchBytes) return CQR_ENOMEM;
+  void* ws = nullptr;
+  if (hipError_t e = cqr::solve_scratch(&ws); e != hipSuccess) return hip_fail(e);
+  return coded_qr_solve(p, Qpost, ldqp, R, ldr, Bpost, ldbp, nrhs, X, ldx, ws, cqr::kSolveScratchBytes, st);
 }
 
 }  // extern "C"

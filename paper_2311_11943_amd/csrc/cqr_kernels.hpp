@@ -224,5 +224,10 @@ void launch_blockdiag(const double* T, double* Y, int64_t ldy, int64_t n, hipStr
 void launch_scale(double* C, int64_t ldc, int64_t rows, int64_t cols, double s, hipStream_t st);
 void launch_trsv_step(const double* R, int64_t ldr, const double* T, double* Y, int64_t ldy, double* X,
                       int64_t ldx, int nrhs, int64_t k0, int w, hipStream_t st);
+// The allocation-free solve's scratch: a file-scope device array of
+// kSolveScratchBytes, one copy per device.  *ptr receives the current
+// device's copy's address (looked up on the first call on each device).
+constexpr size_t kSolveScratchBytes = size_t(32) << 20;
+hipError_t solve_scratch(void** ptr);
 
 }  // namespace cqr

@@ -12,6 +12,8 @@
 //      coalesced across the wave).
 #include "cqr_kernels.hpp"
 
+#include <mutex>
+
 namespace cqr {
 
 constexpr int kSolveThreads = 256;
@@ -165,6 +167,36 @@ void launch_trsv_step(const double* R, int64_t ldr, const double* T, double* Y, 
   const unsigned chunks = (unsigned)((nrhs + kRhsChunk - 1) / kRhsChunk);
   hipLaunchKernelGGL(trsv_step_kernel, dim3(grid, chunks), dim3(kSolveThreads), 0, st, R, ldr, T, Y, ldy, X, ldx,
                      nrhs, k0, w);
+}
+
+// Scratch memory of the allocation-free solve (coded_qr_solve_noalloc): the
+// inverted diagonal blocks of R_1 and Y = Qpost^T Bpost live in this
+// file-scope array, one copy per device, held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): its device address is looked up once per device,
+// with that device current, and that address is what the kernels receive.
+// Every kernel writes the parts of it that later kernels read (trinv_kernel
+// all 64 x 64 entries of each block, gemv_t_kernel all n x nrhs entries of
+// Y), so no call depends on what a previous call left there.
+static __device__ __align__(256) char scratch[kSolveScratchBytes];
+
+hipError_t solve_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = a;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace cqr
