@@ -62,7 +62,7 @@ MFMA_PHASES = {"reproj_product", "reproj_update", "panel_gram", "inpanel_project
 SINGLE_KERNEL_PHASES = ("trailing_product", "trailing_update", "reproj_product", "panel_gram", "recover",
                         "postorth")
 KERNEL_OF = {
-    "encode": "encode_rows_kernel / encode_cols_kernel",
+    "encode": "encode_fused_kernel / encode_rows_kernel",
     "reproj_product": "tn_lds_kernel<1, false>", "reproj_update": "nn_kernel<*, 1>",
     "panel_gram": "tn_lds_kernel<2, false>", "panel_chol": "chol_kernel", "panel_transform": "apply_kernel / nn1_apply_kernel",
     "inpanel_projection": "tn/nn <2, false>",
@@ -766,12 +766,14 @@ def kernel_of(phase: str, b: int, leg: str) -> str:
     """Kernel symbol behind a single-kernel phase (kernels are template-tagged per use)."""
     k = KERNEL_OF[phase]
     if phase == "trailing_update" and b >= 128:
-        k = "nnw16_kernel<0>"            # K = b >= 128: the 16-deep-slab form
+        # K = b >= 128 and every trailing update spans the checksum columns
+        # (>= 256 of them): the 128 x 128-tile form
+        k = "nnq_kernel<0>"
     if phase == "trailing_product" and b > 64:
-        # panels of several tile rows: two tile rows per workgroup (every
-        # trailing product of the n = 32768 workload has >= 4 tile columns)
-        k = "tn2_kernel<0, false>"
-    if phase == "trailing_product" and leg == "fp32":
+        # panels of several tile rows: 128 x 128 per workgroup in FP64, two
+        # tile rows per workgroup for the FP32 product
+        k = "tnq_kernel<0>" if leg != "fp32" else "tn2_kernel<0, true>"
+    elif phase == "trailing_product" and leg == "fp32":
         k = k.replace("<0, false>", "<0, true>")
     return k
 

@@ -566,6 +566,143 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     tn_store(a, acc, tm * a.tilesN + tn, split, w4, lane, tm * 64 + (w4 & 1) * 32, tn * 64 + jb0, F32);
 }
 
+// 128 x 128 output per workgroup (512 threads, 2 x 4 waves, each wave 64
+// rows x 32 columns: a 4 x 2 grid of 16 x 16 MFMA blocks), FP64, 16-deep
+// slabs (72 KB of LDS) with one register set of staged loads (slab s + 1 is
+// requested while slab s is multiplied), two workgroups per CU.  K a
+// multiple of 16 (a masked last slab would not fit the 128 registers).  Each
+// operand column staged is reused by 128 output columns (tn2_kernel: 64 or
+// 128), which halves the L2 requests per flop.  Alone, the K = 49152
+// products with 256 rows run at 67 TFLOP/s against 62 for tn2_kernel (the
+// clock under FP64 MFMA load is ~2.2 GHz, not 2.4, and the MFMA pipes are
+// busy ~80% of those cycles).  The output contract is tn_lds_kernel's on the
+// 64 x 64 tiles the workgroup covers: wave (wi, wj) holds rows 64 wi .. +64
+// and columns 32 wj .. +32, i.e. quadrants (0, wj % 2) and (1, wj % 2) of
+// tile (2 tp + wi, 2 tq + wj / 2).  Tiles are taken with the row index
+// fastest, so the workgroups that read the same columns of B are adjacent.
+template <int TAG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void tnq_kernel(TnArgs a) {
+  constexpr int SK = 16, LW = SK + 2, TPC = SK / 2, CPP = 512 / TPC;   // 8 threads per column, 64 columns a pass
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ double sA[2][128 * LW];
+  __shared__ double sB[2][128 * LW];
+  const int tilesM = a.ntiles / a.tilesN;
+  const int qm = (tilesM + 1) / 2;
+  const int tp = blockIdx.x % qm, tq = blockIdx.x / qm, split = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int wi = wave & 1, wj = wave >> 1;
+  const int ia0 = 64 * wi, jb0 = 32 * wj;
+  const int64_t kb = (int64_t)split * a.kchunk;
+  const int64_t ke = std::min<int64_t>(a.K, kb + a.kchunk);
+  const int lc = tid / TPC, lq = tid % TPC;
+  const double* ga[2];
+  const double* gb[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = tp * 128 + lc + CPP * q, j = tq * 128 + lc + CPP * q;
+    // columns outside the matrix read column 0 and feed only unstored outputs
+    ga[q] = a.A + (int64_t)(i < a.M ? i : 0) * a.lda + 2 * lq;
+    gb[q] = a.B + (int64_t)(j < a.N ? j : 0) * a.ldb + 2 * lq;
+  }
+  v4d acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s0 = 0; s0 < 4; s0 += 2) {
+      double xa[4][2], xb[2][2];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const v2d v = *reinterpret_cast<const v2d*>(&sA[buf][(ia0 + 16 * t + li) * LW + 4 * g + s0]);
+        xa[t][0] = v.x; xa[t][1] = v.y;
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const v2d v = *reinterpret_cast<const v2d*>(&sB[buf][(jb0 + 16 * t + li) * LW + 4 * g + s0]);
+        xb[t][0] = v.x; xb[t][1] = v.y;
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+    }
+  };
+  const int nfull = (int)((ke - kb) / SK);
+  v2d ra[2], rb[2];
+  auto load = [&](int64_t k) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ra[q] = *reinterpret_cast<const v2d*>(ga[q] + k);
+      rb[q] = *reinterpret_cast<const v2d*>(gb[q] + k);
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<v2d*>(&sA[buf][(lc + CPP * q) * LW + 2 * lq]) = ra[q];
+      *reinterpret_cast<v2d*>(&sB[buf][(lc + CPP * q) * LW + 2 * lq]) = rb[q];
+    }
+  };
+  if (nfull > 0) {
+    load(kb);
+    put(0);
+    __syncthreads();
+    for (int sl = 0; sl < nfull; ++sl) {
+      if (sl + 1 < nfull) load(kb + (int64_t)(sl + 1) * SK);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(sl & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (sl + 1 < nfull) put((sl + 1) & 1);
+      __syncthreads();
+    }
+  }
+  // the wave's two quadrants of tile (tm, tn), in tn_lds_kernel's layout
+  const int tm = 2 * tp + wi, tn = 2 * tq + (wj >> 1), ch = wj & 1;
+  if (tm >= tilesM || tn >= a.tilesN) return;
+  const int tile = tm * a.tilesN + tn;
+#pragma unroll
+  for (int xh = 0; xh < 2; ++xh) {
+    const int quadrant = xh + 2 * ch;
+    if (a.nsplit > 1) {
+      double* mine = a.part + part_off(split, a.ntiles, tile, quadrant);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine[((x * 2 + y) * 4 + r) * 64 + lane] = acc[2 * xh + x][y][r];
+    } else {
+      // one 16 x 16 block at a time (its C2 loads issued before its stores)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int i = tm * 64 + 32 * xh + 16 * x + li;
+          const int j0 = tn * 64 + 32 * ch + 16 * y;
+          double old[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + colsub(r, g, false);
+            old[r] = (a.C2 && i < a.M2 && j < a.N) ? a.C2[i + (int64_t)j * a.ldc2] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + colsub(r, g, false);
+            const double v = acc[2 * xh + x][y][r];
+            if (i < a.M && j < a.N) {
+              a.C[i + (int64_t)j * a.ldc] = v;
+              if (a.C2 && i < a.M2) a.C2[i + (int64_t)j * a.ldc2] = old[r] + v;
+            }
+          }
+        }
+    }
+  }
+}
+
 // Fallback for operands that are not 16-byte aligned or have odd leading
 // dimensions: direct scalar loads, same tiling and output contract.
 __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
@@ -673,8 +810,11 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   // two tile rows per workgroup from two tile rows and four tile columns on
   // (with fewer tile columns the re-projections on the panel chain slow down)
   const bool pair = vec && tilesM >= 2 && tilesN >= 4;
+  // FP64 products of at least two tile rows and columns: 128 x 128 per workgroup
+  // and a depth that is a multiple of 16 (whole slabs in every split)
+  const bool quad = vec && !f32 && tilesM >= 2 && tilesN >= 2 && K % 16 == 0;
   // the split count fills the grid of workgroups the product launches
-  const int blocks = pair ? (tilesM + 1) / 2 * tilesN : tiles;
+  const int blocks = quad ? (tilesM + 1) / 2 * ((tilesN + 1) / 2) : pair ? (tilesM + 1) / 2 * tilesN : tiles;
   int ns = force_split > 0 ? force_split : pick_split(blocks, K, s.npart);
   while (ns > 1 && (int64_t)ns * tiles > s.npart) --ns;
   int64_t kchunk = (K + ns - 1) / ns;
@@ -684,7 +824,8 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   a.part = s.part;
   a.vec = vec;
   a.f32 = f32 && a.vec;     // the FP32 form exists for the LDS-staged kernel
-  a.pair = pair;
+  a.pair = pair && !quad;
+  a.quad = quad;
   return a;
 }
 
@@ -693,6 +834,15 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
   const dim3 grid(a.ntiles, a.nsplit);
   if (!a.vec) {
     hipLaunchKernelGGL(tn_direct_kernel, grid, dim3(256), 0, st, a);
+    return;
+  }
+  if (a.quad) {
+    const dim3 gridq((unsigned)((a.ntiles / a.tilesN + 1) / 2 * ((a.tilesN + 1) / 2)), a.nsplit);
+    switch (tag) {
+      case TAG_TRAIL: hipLaunchKernelGGL((tnq_kernel<TAG_TRAIL>), gridq, dim3(512), 0, st, a); break;
+      case TAG_REPROJ: hipLaunchKernelGGL((tnq_kernel<TAG_REPROJ>), gridq, dim3(512), 0, st, a); break;
+      default: hipLaunchKernelGGL((tnq_kernel<TAG_PANEL>), gridq, dim3(512), 0, st, a); break;
+    }
     return;
   }
   if (a.pair) {
@@ -1352,6 +1502,8 @@ void launch_apply(double* P, int64_t ldp, int64_t mrows, int w, const Scratch& s
 // --------------------------------------------------------------------------
 
 constexpr int NK = 64;   // k per slab of the rank-K update
+// Fewest columns for which the update takes the 128 x 128 kernel.
+constexpr int kQuadMinN = 256;
 
 // Shared pieces of the rank-K update kernels.  B staging: thread t moves
 // B[k0 + 16(t & 3) + e][jb + (t >> 2)], e < 16 (8 vector loads from one
@@ -1937,6 +2089,119 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   nnw_body<TAG, 16>(a, sA, sB);
 }
 
+// 128 x 128 output tile per workgroup (512 threads, 2 x 4 waves, each wave
+// 64 rows x 32 columns), 16-deep slabs double-buffered in LDS (72 KB) with
+// one register set of staged loads, two workgroups per CU: K >= 128.  Each
+// staged column of A and row of B feeds 128 outputs instead of 64, which
+// halves the L2 requests per flop against nnw16_kernel.  Alone, the
+// K = 256 update of a 49152 x 32768 C runs at 58.7 TFLOP/s against 51.3
+// (K = 128, 32768 x 20480: 48.1 against 41.1).  A (i contiguous) is
+// transposed into the [i][k] LDS layout as it is staged; C is read after
+// the K loop, one 16-row block at a time, and written back in place.
+// Requires K a multiple of 16, 16-byte aligned A and B with even leading
+// dimensions, and an even M; tiles take the XCD-aware order.
+template <int TAG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void nnq_kernel(NnArgs a) {
+  constexpr int SK = 16, LW = SK + 2;
+  constexpr int AKR = 8;               // A staging: k rows per pass (64 row pairs x 8)
+  constexpr int TPC = SK / 2, CPP = 512 / TPC;   // B staging: 8 threads per column, 64 columns a pass
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ double sA[2][128 * LW];
+  __shared__ double sB[2][128 * LW];
+  const int tilesM = (int)((a.M + 127) / 128), tilesN = (a.N + 127) / 128;
+  int tm, tn;
+  xcd_tile(blockIdx.x, tilesM * tilesN, tilesM, tilesN, tm, tn);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int ia0 = 64 * (wave & 1), jb0 = 32 * (wave >> 1);
+  const int64_t ib = (int64_t)tm * 128, jb = (int64_t)tn * 128;
+  const int ip = tid & 63, kr = tid >> 6;
+  const int64_t ia = ib + 2 * ip;
+  const double* ga = a.A + (ia + 1 < a.M ? ia : 0) + (int64_t)kr * a.lda;
+  const int lc = tid / TPC, lq = tid % TPC;
+  const double* gb[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int64_t j = jb + lc + CPP * q;
+    gb[q] = a.B + (j < a.N ? j : 0) * a.ldb + 2 * lq;
+  }
+  v4d acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s0 = 0; s0 < 4; s0 += 2) {
+      double xa[4][2], xb[2][2];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const v2d v = *reinterpret_cast<const v2d*>(&sA[buf][(ia0 + 16 * t + li) * LW + 4 * g + s0]);
+        xa[t][0] = v.x; xa[t][1] = v.y;
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const v2d v = *reinterpret_cast<const v2d*>(&sB[buf][(jb0 + 16 * t + li) * LW + 4 * g + s0]);
+        xb[t][0] = v.x; xb[t][1] = v.y;
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma(xb[y][s], xa[x][s], acc[x][y]);
+    }
+  };
+  const int nsl = a.K / SK;
+  v2d ra[2], rb[2];
+  auto load = [&](int64_t k) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ra[q] = *reinterpret_cast<const v2d*>(ga + (k + AKR * q) * a.lda);
+      rb[q] = *reinterpret_cast<const v2d*>(gb[q] + k);
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      sA[buf][(2 * ip) * LW + kr + AKR * q] = ra[q].x;
+      sA[buf][(2 * ip + 1) * LW + kr + AKR * q] = ra[q].y;
+      *reinterpret_cast<v2d*>(&sB[buf][(lc + CPP * q) * LW + 2 * lq]) = rb[q];
+    }
+  };
+  load(0);
+  put(0);
+  __syncthreads();
+  for (int sl = 0; sl < nsl; ++sl) {
+    if (sl + 1 < nsl) load((int64_t)(sl + 1) * SK);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(sl & 1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (sl + 1 < nsl) put((sl + 1) & 1);
+    __syncthreads();
+  }
+  // C -= acc, one 16-row block of the wave's 64 rows at a time; rows and
+  // columns outside C read row or column 0 and are not stored
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int64_t i = ib + ia0 + 16 * x + li;
+    double cv[2][4];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = jb + jb0 + 16 * y + colsub(r, g, false);
+        cv[y][r] = a.C[(i < a.M ? i : 0) + (j < a.N ? j : 0) * a.ldc];
+      }
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = jb + jb0 + 16 * y + colsub(r, g, false);
+        if (i < a.M && j < a.N) a.C[i + j * a.ldc] = cv[y][r] - acc[x][y][r];
+      }
+  }
+}
+
 // Operands the LDS-staged update takes, K >= 64 (else the register-staged
 // kernels): 18-22% faster standalone than the register-staged long-K kernel
 // at K = 128 and 256.  At K = 64 it is ~8% slower alone than nn1_kernel but
@@ -1945,12 +2210,21 @@ static bool nnw_ok(const NnArgs& a) {
   return a.K >= NK && a.K % KC == 0 && a.M % 2 == 0 && aligned16(a.A, a.lda) && aligned16(a.B, a.ldb);
 }
 
+// The 128 x 128 update: K >= 128 and at least two 128-wide tiles each way
+// (see kQuadMinN for the column count).
+static bool nnq_ok(const NnArgs& a) {
+  return nnw_ok(a) && a.K >= 2 * NK && a.M >= 256 && a.N >= kQuadMinN;
+}
+
 template <int TAG>
 static void nn_launch_tag(const NnArgs& a, hipStream_t st) {
   if (a.K <= NK && !nnw_ok(a))
     hipLaunchKernelGGL((nn1_kernel<TAG>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (a.nsplit > 1)
     hipLaunchKernelGGL((nn_kernel<true, TAG>), dim3(a.ntiles, a.nsplit), dim3(256), 0, st, a);
+  else if (nnq_ok(a))
+    hipLaunchKernelGGL((nnq_kernel<TAG>), dim3((unsigned)(((a.M + 127) / 128) * ((a.N + 127) / 128))), dim3(512), 0,
+                       st, a);
   else if (nnw_ok(a) && a.K >= 2 * NK)
     hipLaunchKernelGGL((nnw16_kernel<TAG>), dim3(a.ntiles), dim3(256), 0, st, a);
   else if (nnw_ok(a))

@@ -97,6 +97,7 @@ struct TnArgs {
                       // k-values, FP64 sums across those groups
   int prio;           // raise the waves' issue priority (panel-chain products)
   int pair;           // two tile rows per 512-thread workgroup (tn2_kernel)
+  int quad;           // 128 x 128 output per 512-thread workgroup (tnq_kernel, FP64)
 };
 
 // Choose the split of C = A^T B (stored to C; rows below M2 -- all rows
