@@ -759,6 +759,10 @@ PRECISIONS = {
     "fp32": {"code": 1, "dtype": "f64 (R_bar on FP32 MFMA)",
              "desc": "coefficient product R_bar = Qbar^T Q_t on FP32 MFMA (FP32 sums over 16 k-values, FP64 "
                      "across them); rank-b update, re-projection, panels, decode, post-orth in FP64"},
+    "bf16x3": {"code": 2, "dtype": "f64 (R_bar as split-BF16 products on BF16 MFMA)",
+               "desc": "coefficient product R_bar = Qbar^T Q_t with each FP64 operand split into three BF16 parts, "
+                       "six part products on BF16 MFMA (FP32 sums over 32 k-values, FP64 across them); rank-b "
+                       "update, re-projection, panels, decode, post-orth in FP64"},
 }
 
 

@@ -53,7 +53,12 @@ typedef enum { CQR_OUT_OF_NODE = 0, CQR_IN_NODE = 1 } cqr_storage;
  * (not in the paper: a growth direction).  CQR_FP64: everything in FP64.
  * CQR_TRAIL_FP32: R_bar (and the early update's Qbar1^T Q_t) on FP32 MFMA,
  * operands rounded to FP32, FP32 sums over 16 k-values and FP64 sums across
- * them.  In every mode the column operations
+ * them.  CQR_TRAIL_BF16X3: the same products split into BF16 parts (each FP64
+ * operand x = hi + mid + lo to 2^-26 |x|; the six part products of size at
+ * least 2^-16 of the whole on BF16 MFMA, FP32 sums over 32 k-values, FP64
+ * sums across them) where the product has at least two 64-row and two
+ * 64-column tiles and a depth that is a multiple of 32 (the trailing products
+ * of panels wider than 64 columns), FP32 otherwise.  In every mode the column operations
  * on A~ -- the rank-b update Q_t -= Qbar R_bar, the re-projection and the
  * panel factorization -- run in FP64 with the coefficients R records, so the
  * checksum rows are carried (Q_2 = G_v Q_1 to FP64 rounding, nothing is
@@ -61,7 +66,7 @@ typedef enum { CQR_OUT_OF_NODE = 0, CQR_IN_NODE = 1 } cqr_storage;
  * the next panels removes what the reduced-precision R_bar leaves behind.  The
  * R-side relation R_2 = R_1 G_h holds for finished columns to FP64 rounding
  * and for unfinished columns to the accuracy of R_bar, which bounds the error
- * of R blocks decoded mid-factorization.  CQR_TRAIL_BF16X3 is reserved. */
+ * of R blocks decoded mid-factorization. */
 typedef enum { CQR_FP64 = 0, CQR_TRAIL_FP32 = 1, CQR_TRAIL_BF16X3 = 2 } cqr_precision;
 
 /* How each panel is orthogonalised (appendix algorithms PBMGS, CGS,

@@ -335,9 +335,9 @@ double partial_bytes(int nsplit, int ntiles) { return 8.0 * nsplit * ntiles * cq
 
 void tn(cqr_plan_s& p, int phase, const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N,
         int64_t K, double* C, int64_t ldc, double* C2, int64_t ldc2, const cqr::Scratch& s, hipStream_t st,
-        int M2 = -1, bool f32 = false) {
+        int M2 = -1, int lowp = 0) {
   if (M <= 0 || N <= 0) return;
-  cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s, 0, f32);
+  cqr::TnArgs a = cqr::tn_setup(A, lda, B, ldb, M, N, K, C, ldc, C2, ldc2, s, 0, lowp);
   if (M2 >= 0) a.M2 = M2;
   a.prio = chain_phase(phase);
   const double fl = 2.0 * M * N * (double)K, by = 8.0 * ((double)K * M + (double)K * N);
@@ -407,10 +407,10 @@ void colpanel(cqr_plan_s& p, double* P, int64_t ldq, int w, double* Rout, int64_
 // free slots (measured: 448 beats 512 by 2% on the n = 4096 step).
 constexpr int kEarlyBlocks = 448;
 cqr::TnArgs tn_early(cqr_plan_s& p, const double* X, int64_t ldx, const double* B, int64_t ldb, int w, int N,
-                     const cqr::Scratch& s, hipStream_t st, bool f32) {
+                     const cqr::Scratch& s, hipStream_t st, int lowp) {
   const int tiles = (N + kTile - 1) / kTile;
   const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(kEarlyBlocks / tiles, p.mp / 256));
-  cqr::TnArgs a = cqr::tn_setup(X, ldx, B, ldb, w, N, p.mp, s.part, w, nullptr, 0, s, ns, f32);
+  cqr::TnArgs a = cqr::tn_setup(X, ldx, B, ldb, w, N, p.mp, s.part, w, nullptr, 0, s, ns, lowp);
   a.prio = chain_phase(PH_TRAIL_TN);
   const double fl = 2.0 * w * N * (double)p.mp, by = 8.0 * (double)p.mp * ((double)w + N);
   const double out = a.nsplit > 1 ? partial_bytes(a.nsplit, a.ntiles) : 8.0 * (double)w * N;
@@ -542,7 +542,7 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   if (c.kv > 0 && 2 * c.kv > c.pr) return CQR_EINVAL;        // post-orthogonalization needs K_v <= p_r/2
   if (c.kh > c.pc && c.storage == CQR_IN_NODE) return CQR_EINVAL;
   if (c.storage != CQR_OUT_OF_NODE && c.storage != CQR_IN_NODE) return CQR_EINVAL;
-  if (c.precision != CQR_FP64 && c.precision != CQR_TRAIL_FP32) return CQR_EINVAL;
+  if (c.precision != CQR_FP64 && c.precision != CQR_TRAIL_FP32 && c.precision != CQR_TRAIL_BF16X3) return CQR_EINVAL;
   if (c.panel < CQR_PANEL_CHOLQR2 || c.panel > CQR_PANEL_MGS) return CQR_EINVAL;
   if (!(c.icgs_eta >= 0.0 && c.icgs_eta <= 1.0)) return CQR_EINVAL;   // also rejects NaN
   if (c.lookahead != 0 && c.lookahead != 1) return CQR_EINVAL;
@@ -726,7 +726,9 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
     st = p->chain;
   }
   // Mixed precision: the coefficient products R_bar = Qbar^T Q_t of the
-  // trailing update (and of the early update) run on FP32 MFMA.  Every column
+  // trailing update (and of the early update) run on FP32 MFMA, or as
+  // split-BF16 products on BF16 MFMA (FP32 where the product's shape does
+  // not suit the split kernel).  Every column
   // operation on the encoded matrix -- the rank-b update Q_t -= Qbar R_bar, the
   // re-projection, the panel transforms -- stays FP64: a column operation
   // applied with the same coefficients to every row keeps Q_2 = G_v Q_1 to
@@ -735,13 +737,13 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
   // FP32 error of R_bar leaves components of Qbar in the trailing columns;
   // the next panels' FP64 re-projection removes them and adds their
   // coefficients into R.
-  const bool f32 = p->cfg.precision == CQR_TRAIL_FP32;
+  const int lowp = p->cfg.precision == CQR_TRAIL_FP32 ? 1 : p->cfg.precision == CQR_TRAIL_BF16X3 ? 2 : 0;
   // Panel k's update of columns [from, to):  R_bar = Qbar^T Q_t -> R[panel, from:];  Q_t -= Qbar R_bar
   auto trail = [&](int64_t c0, int64_t from, int64_t to, const cqr::Scratch& sc, hipStream_t ss) {
     double* Rb = R + c0 + from * ldr;
     const double* P = Q + c0 * ldq;
     tn(*p, PH_TRAIL_TN, P, ldq, Q + from * ldq, ldq, (int)b, (int)(to - from), mp, Rb, ldr, nullptr, 0, sc, ss, -1,
-       f32);
+       lowp);
     nn(*p, PH_TRAIL_NN, Q + from * ldq, ldq, P, ldq, Rb, ldr, mp, (int)(to - from), (int)b, sc, ss);
   };
   bool deferred = false;       // a wide panel's update of the columns after the next panel, not yet forked
@@ -830,7 +832,7 @@ cqr_status coded_qr_factor(cqr_plan p, double* Q, int64_t ldq, double* R, int64_
       cqr::TnArgs ea{};
       if (early) {
         if (hipError_t e = hipStreamWaitEvent(p->side, p->ev_main, 0); e != hipSuccess) return hip_fail(e);
-        ea = tn_early(*p, X, s.ldx, Q + (c1 + b) * ldq, ldq, (int)b, (int)(N - c1 - b), s2, p->side, f32);
+        ea = tn_early(*p, X, s.ldx, Q + (c1 + b) * ldq, ldq, (int)b, (int)(N - c1 - b), s2, p->side, lowp);
       }
       tn(*p, PH_GRAM, P, ldq, P, ldq, (int)b, next ? 2 * (int)b : (int)b, mp, s.G, b, nullptr, 0, s, st);
       chol(*p, s.G, b, (int)b, 2, R + c0 + c0 * ldr, ldr, next ? s.G + b * b : nullptr, b,

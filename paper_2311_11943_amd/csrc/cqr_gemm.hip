@@ -703,6 +703,176 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   }
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// x = hi + mid + lo + e with BF16 parts, each the rounding of what the parts
+// before it leave (through FP32), |e| <= 2^-26 |x|: the differences x - hi
+// and x - hi - mid are exact in FP64 (each part is within a factor 2^-8 of
+// what it approximates).
+__device__ __forceinline__ void split3(double x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)(float)x;
+  const double r1 = x - (double)(float)h;
+  m = (__bf16)(float)r1;
+  const double r2 = r1 - (double)(float)m;
+  l = (__bf16)(float)r2;
+}
+
+// D += X Y on BF16 MFMA, 16 x 16 x 32 (lane l supplies 8 k-values of row l % 16
+// of X and of column l % 16 of Y; FP32 result in the f32 layout)
+__device__ __forceinline__ v4f mfma_bf(const bf16x8& x, const bf16x8& y, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+}
+
+// Split-BF16 form of tnq_kernel (the mixed-precision coefficient product
+// R_bar = Qbar^T Q_t): 128 x 128 output per 512-thread workgroup, each wave a
+// 64 x 32 block.  Slabs are 32 deep.  Every staged FP64 element is split
+// into three BF16 parts (split3) as it is stored to LDS, into three planes
+// per operand (k contiguous, 80-byte column pitch: conflict-free 16-byte
+// reads); the product of two elements is taken as the six part products
+// whose size is at least 2^-16 of the whole (hi hi, hi mid, mid hi, hi lo,
+// lo hi, mid mid; the three dropped ones are below 2^-25 of it), issued
+// smallest first into one FP32 accumulator per 32-k slab, which is then
+// added into the FP64 accumulators.  Two LDS buffers (120 KB): one
+// workgroup per CU, two waves per SIMD.  K a multiple of 32.
+template <int TAG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void tnb_kernel(TnArgs a) {
+  constexpr int SK = 32, LW = SK + 8, TPC = SK / 2, CPP = 512 / TPC;   // 16 threads per column, 32 columns a pass
+  constexpr int PL = 128 * LW;                                         // one plane of one operand
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ __bf16 sA[2][3 * PL];
+  __shared__ __bf16 sB[2][3 * PL];
+  const int tilesM = a.ntiles / a.tilesN;
+  const int qm = (tilesM + 1) / 2;
+  const int tp = blockIdx.x % qm, tq = blockIdx.x / qm, split = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int wi = wave & 1, wj = wave >> 1;
+  const int ia0 = 64 * wi, jb0 = 32 * wj;
+  const int64_t kb = (int64_t)split * a.kchunk;
+  const int64_t ke = std::min<int64_t>(a.K, kb + a.kchunk);
+  const int lc = tid / TPC, lq = tid % TPC;
+  const double* ga[4];
+  const double* gb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = tp * 128 + lc + CPP * q, j = tq * 128 + lc + CPP * q;
+    // columns outside the matrix read column 0 and feed only unstored outputs
+    ga[q] = a.A + (int64_t)(i < a.M ? i : 0) * a.lda + 2 * lq;
+    gb[q] = a.B + (int64_t)(j < a.N ? j : 0) * a.ldb + 2 * lq;
+  }
+  v4d acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+  auto compute = [&](int buf) {
+    bf16x8 fb[2][3];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl)
+        fb[y][pl] = *reinterpret_cast<const bf16x8*>(&sB[buf][pl * PL + (jb0 + 16 * y + li) * LW + 8 * g]);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      bf16x8 fa[3];
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl)
+        fa[pl] = *reinterpret_cast<const bf16x8*>(&sA[buf][pl * PL + (ia0 + 16 * x + li) * LW + 8 * g]);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        // issued transposed (B's part first), smallest part products first
+        v4f t = v4f{0, 0, 0, 0};
+        t = mfma_bf(fb[y][2], fa[0], t);
+        t = mfma_bf(fb[y][0], fa[2], t);
+        t = mfma_bf(fb[y][1], fa[1], t);
+        t = mfma_bf(fb[y][1], fa[0], t);
+        t = mfma_bf(fb[y][0], fa[1], t);
+        t = mfma_bf(fb[y][0], fa[0], t);
+        widen_add(acc[x][y], t);
+      }
+    }
+  };
+  const int nsl = (int)((ke - kb) / SK);
+  v2d ra[4], rb[4];
+  auto load = [&](int64_t k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = *reinterpret_cast<const v2d*>(ga[q] + k);
+      rb[q] = *reinterpret_cast<const v2d*>(gb[q] + k);
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __bf16 h0, m0, l0, h1, m1, l1;
+      const int off = (lc + CPP * q) * LW + 2 * lq;
+      split3(ra[q].x, h0, m0, l0);
+      split3(ra[q].y, h1, m1, l1);
+      *reinterpret_cast<bf16x2*>(&sA[buf][off]) = bf16x2{h0, h1};
+      *reinterpret_cast<bf16x2*>(&sA[buf][PL + off]) = bf16x2{m0, m1};
+      *reinterpret_cast<bf16x2*>(&sA[buf][2 * PL + off]) = bf16x2{l0, l1};
+      split3(rb[q].x, h0, m0, l0);
+      split3(rb[q].y, h1, m1, l1);
+      *reinterpret_cast<bf16x2*>(&sB[buf][off]) = bf16x2{h0, h1};
+      *reinterpret_cast<bf16x2*>(&sB[buf][PL + off]) = bf16x2{m0, m1};
+      *reinterpret_cast<bf16x2*>(&sB[buf][2 * PL + off]) = bf16x2{l0, l1};
+    }
+  };
+  if (nsl > 0) {
+    load(kb);
+    put(0);
+    __syncthreads();
+    for (int sl = 0; sl < nsl; ++sl) {
+      if (sl + 1 < nsl) load(kb + (int64_t)(sl + 1) * SK);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(sl & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (sl + 1 < nsl) put((sl + 1) & 1);
+      __syncthreads();
+    }
+  }
+  // the wave's two quadrants of tile (tm, tn), in tn_lds_kernel's layout (f32 form)
+  const int tm = 2 * tp + wi, tn = 2 * tq + (wj >> 1), ch = wj & 1;
+  if (tm >= tilesM || tn >= a.tilesN) return;
+  const int tile = tm * a.tilesN + tn;
+#pragma unroll
+  for (int xh = 0; xh < 2; ++xh) {
+    const int quadrant = xh + 2 * ch;
+    if (a.nsplit > 1) {
+      double* mine = a.part + part_off(split, a.ntiles, tile, quadrant);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine[((x * 2 + y) * 4 + r) * 64 + lane] = acc[2 * xh + x][y][r];
+    } else {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int i = tm * 64 + 32 * xh + 16 * x + li;
+          const int j0 = tn * 64 + 32 * ch + 16 * y;
+          double old[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + colsub(r, g, true);
+            old[r] = (a.C2 && i < a.M2 && j < a.N) ? a.C2[i + (int64_t)j * a.ldc2] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + colsub(r, g, true);
+            const double v = acc[2 * xh + x][y][r];
+            if (i < a.M && j < a.N) {
+              a.C[i + (int64_t)j * a.ldc] = v;
+              if (a.C2 && i < a.M2) a.C2[i + (int64_t)j * a.ldc2] = old[r] + v;
+            }
+          }
+        }
+    }
+  }
+}
+
 // Fallback for operands that are not 16-byte aligned or have odd leading
 // dimensions: direct scalar loads, same tiling and output contract.
 __global__ __launch_bounds__(256) void tn_direct_kernel(TnArgs a) {
@@ -800,7 +970,8 @@ static int pick_split(int tiles, int64_t K, int64_t cap) {
 }
 
 TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
-                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split, bool f32) {
+                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split, int lowp) {
+  const bool f32 = lowp != 0;
   TnArgs a{};
   a.A = A; a.lda = lda; a.B = B; a.ldb = ldb;
   a.C = C; a.ldc = ldc; a.C2 = C2; a.ldc2 = ldc2; a.M2 = M;
@@ -813,8 +984,10 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   // FP64 products of at least two tile rows and columns: 128 x 128 per workgroup
   // and a depth that is a multiple of 16 (whole slabs in every split)
   const bool quad = vec && !f32 && tilesM >= 2 && tilesN >= 2 && K % 16 == 0;
+  // the split-BF16 product on the same 128 x 128 tiles
+  const bool bf3 = vec && lowp == 2 && tilesM >= 2 && tilesN >= 2 && K % 32 == 0;
   // the split count fills the grid of workgroups the product launches
-  const int blocks = quad ? (tilesM + 1) / 2 * ((tilesN + 1) / 2) : pair ? (tilesM + 1) / 2 * tilesN : tiles;
+  const int blocks = quad || bf3 ? (tilesM + 1) / 2 * ((tilesN + 1) / 2) : pair ? (tilesM + 1) / 2 * tilesN : tiles;
   int ns = force_split > 0 ? force_split : pick_split(blocks, K, s.npart);
   while (ns > 1 && (int64_t)ns * tiles > s.npart) --ns;
   int64_t kchunk = (K + ns - 1) / ns;
@@ -824,8 +997,9 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   a.part = s.part;
   a.vec = vec;
   a.f32 = f32 && a.vec;     // the FP32 form exists for the LDS-staged kernel
-  a.pair = pair && !quad;
+  a.pair = pair && !quad && !bf3;
   a.quad = quad;
+  a.bf3 = bf3;
   return a;
 }
 
@@ -834,6 +1008,11 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
   const dim3 grid(a.ntiles, a.nsplit);
   if (!a.vec) {
     hipLaunchKernelGGL(tn_direct_kernel, grid, dim3(256), 0, st, a);
+    return;
+  }
+  if (a.bf3) {
+    const dim3 gridb((unsigned)((a.ntiles / a.tilesN + 1) / 2 * ((a.tilesN + 1) / 2)), a.nsplit);
+    hipLaunchKernelGGL((tnb_kernel<TAG_TRAIL>), gridb, dim3(512), 0, st, a);
     return;
   }
   if (a.quad) {

@@ -98,16 +98,21 @@ struct TnArgs {
   int prio;           // raise the waves' issue priority (panel-chain products)
   int pair;           // two tile rows per 512-thread workgroup (tn2_kernel)
   int quad;           // 128 x 128 output per 512-thread workgroup (tnq_kernel, FP64)
+  int bf3;            // split-BF16 product (tnb_kernel): each FP64 operand as hi + mid + lo
+                      // BF16 parts, six part products on BF16 MFMA with FP32 sums over
+                      // 32 k-values, FP64 sums across them (output layout as f32)
 };
 
 // Choose the split of C = A^T B (stored to C; rows below M2 -- all rows
 // unless changed -- also added into C2 if C2 != nullptr).
 // force_split > 0 fixes the split count (capped by the partial capacity).
-// f32: the product on FP32 MFMA (operands rounded to FP32, FP32 sums over 16
-// k-values, FP64 sums across them), for the mixed-precision coefficient
+// lowp: 1 = the product on FP32 MFMA (operands rounded to FP32, FP32 sums over
+// 16 k-values, FP64 sums across them); 2 = split BF16 (tnb_kernel) where the
+// shape allows it (at least two tile rows and columns, depth a multiple of
+// 32, aligned operands), else FP32; for the mixed-precision coefficient
 // product R_bar = Qbar^T Q_t.
 TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int64_t K, double* C,
-                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0, bool f32 = false);
+                int64_t ldc, double* C2, int64_t ldc2, const Scratch& s, int force_split = 0, int lowp = 0);
 // The product; with nsplit == 1 it stores C (and C2) itself, else partials.
 void launch_tn_product(const TnArgs& a, int tag, hipStream_t st);
 // Sum the partials into C (and C2) in split order (nsplit > 1 only).

@@ -103,7 +103,6 @@ def test_plan_generators_and_tolerance_match_oracle(pr, pc, kv, kh, storage):
     dict(kv=9),                     # too many checksums
     dict(kv=3),                     # post-orthogonalization needs K_v <= p_r / 2
     dict(precision=7),              # unknown precision
-    dict(precision=2),              # reserved precision
     dict(storage=5),                # unknown storage
     dict(panel=4),                  # unknown panel mode
     dict(icgs_eta=1.5),             # ICGS threshold above 1
@@ -121,8 +120,9 @@ def test_plan_create_rejects_invalid_configs(bad):
     assert e.value.status == cqr.CQR_EINVAL
 
 
-def test_plan_accepts_fp32_trailing_precision():
-    cfg = cqr.Config(m=256, n=256, pr=4, pc=4, kv=1, kh=1, b=16, precision=cqr.CQR_TRAIL_FP32)
+@pytest.mark.parametrize("precision", ["CQR_TRAIL_FP32", "CQR_TRAIL_BF16X3"])
+def test_plan_accepts_reduced_precision_products(precision):
+    cfg = cqr.Config(m=256, n=256, pr=4, pc=4, kv=1, kh=1, b=16, precision=getattr(cqr, precision))
     p = cqr.coded_qr_plan_create(cfg, synth.q_generator_draws(1, 4, 1), synth.r_generator_draws(4, 1, 1))
     cqr.coded_qr_plan_destroy(p)
 

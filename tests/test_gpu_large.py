@@ -12,7 +12,8 @@ failure schedules), by properties that hold at any size:
 
 n = 16384 (8 x 8 grid, b = 128, K = 4 out-of-node, A = U diag(s) V^T with
 cond 1e6, a reverse-diagonal storm of 4 nodes per grid row every 16 panels) in
-FP64 and with the coefficient product on FP32 MFMA; n = 32768 (16 x 16 grid, b = 256, K = 8
+FP64 and with the coefficient product on FP32 MFMA and as split-BF16
+products; n = 32768 (16 x 16 grid, b = 256, K = 8
 in-node, Gaussian A, storms of 4 nodes per row) in FP64.  The oracle cannot
 run at these sizes; the n = 4096 workload is compared with it element by
 element in test_gpu_fullsize.py.
@@ -112,7 +113,7 @@ def _properties(q, A_dev, At, R):
     return res, orth, worst, orth_post
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_n16384_properties(precision):
     import bench
     from oracle import coded_qr as oc
@@ -125,7 +126,7 @@ def test_n16384_properties(precision):
     print(f"[case] n = {n}, {precision}, schedule {inp['schedule']}", flush=True)
     dev = torch.device("cuda:0")
     A_dev = cqr.to_device_colmajor(bench.conditioned_input(n, 1e6, 0, dev), dev)
-    prec = cqr.CQR_TRAIL_FP32 if precision == "fp32" else cqr.CQR_FP64
+    prec = {"fp64": cqr.CQR_FP64, "fp32": cqr.CQR_TRAIL_FP32, "bf16x3": cqr.CQR_TRAIL_BF16X3}[precision]
     q = cqr.CodedQR(cqr.Config(n, n, pr, pr, K, K, b, cqr.CQR_OUT_OF_NODE, lookahead=1, precision=prec),
                     inp["v"], inp["gh"], dev)
     At, R, (rec_fin, rec_q, rec_r, r_ratio) = _run_checked(q, A_dev, inp["schedule"])
@@ -142,8 +143,8 @@ def test_n16384_properties(precision):
     if precision == "fp64":
         assert rec_r <= 1e-10 and res <= 1e-12
     else:
-        # R's checksum relation holds to the accuracy of the FP32 coefficient
-        # product for unfinished columns; a decoded R block carries that error
+        # R's checksum relation holds to the accuracy of the reduced-precision
+        # coefficient product for unfinished columns; a decoded R block carries that error
         # through the decode solve, and no further
         assert r_ratio <= 1.0
         assert res <= 1e-6

@@ -1,5 +1,6 @@
 """Mixed precision (the coefficient product R_bar = Qbar^T Q_t on FP32 MFMA,
-every column operation in FP64) against the FP64 oracle.
+or as split-BF16 products on BF16 MFMA, every column operation in FP64)
+against the FP64 oracle.
 
 What the arithmetic fixes, and so what is asserted:
   * The rank-b update, the re-projection and the panel transforms are FP64
@@ -19,6 +20,11 @@ What the arithmetic fixes, and so what is asserted:
     sums over s = 16 terms, FP64 across), and a checksum column collects one
     per row of R, so ||R_2 - R_1 G_h||_F <= (s + 2) u32 sqrt(n) ||R_2||_F.  The
     same bound holds for the carried residual Q~ (R_1 G_h - R_2).
+  * The split-BF16 form: each FP64 operand is hi + mid + lo to 2^-26 of
+    itself, and the three part products it drops are below 2^-25 of the
+    whole, so the parts represent each product to about u32; the five small
+    part products are summed first, so the FP32 rounding is that of the
+    hi hi sum over s = 32 k-values: (s + 3) u32 per coefficient.
   * An R block decoded mid-factorization inherits that relation's error
     through the decode solve: its error is G_hat^{-1} applied to the relation
     error of the surviving checksums, checked against the snapshot taken
@@ -36,11 +42,18 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 U32 = 2.0 ** -24          # unit roundoff of FP32
-S_GROUP = 16              # k-values summed in FP32 before the FP64 sum
+# k-values summed in FP32 before the FP64 sum, and the u32 terms per
+# coefficient beyond them (operand rounding; for the split form the split)
+TERMS = {"fp32": (16, 2), "bf16x3": (32, 3)}
 
 
-def r_relation_bound(n: int) -> float:
-    return (S_GROUP + 2) * U32 * np.sqrt(n)
+def r_relation_bound(n: int, precision: str = "fp32") -> float:
+    s, extra = TERMS[precision]
+    return (s + extra) * U32 * np.sqrt(n)
+
+
+def _code(cqr, precision):
+    return cqr.CQR_TRAIL_FP32 if precision == "fp32" else cqr.CQR_TRAIL_BF16X3
 
 
 @pytest.fixture(scope="module")
@@ -66,11 +79,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("sid,n,pr,K,b,storage,kind,cond", CASES, ids=[c[0] for c in CASES])
-def test_fp32_coefficients_match_fp64_oracle(cqr, sid, n, pr, K, b, storage, kind, cond):
-    print(f"[case] mixed {sid}", flush=True)
+def test_reduced_precision_coefficients_match_fp64_oracle(cqr, sid, n, pr, K, b, storage, kind, cond, precision):
+    # the split-BF16 product needs two tile rows and a depth that is a multiple
+    # of 32; the other cases run its FP32 fallback, checked here all the same
+    print(f"[case] mixed {precision} {sid}", flush=True)
     A, v, gh, lay = make_inputs(n, pr, K, b, storage, seed=8, kind=kind, cond=cond)
-    cfg = gpu_config(cqr, lay, b, precision=cqr.CQR_TRAIL_FP32)
+    cfg = gpu_config(cqr, lay, b, precision=_code(cqr, precision))
     q = cqr.CodedQR(cfg, v, gh)
     At, R, _, _ = q.run(cqr.to_device_colmajor(A, "cuda:0"))
     torch.cuda.synchronize()
@@ -107,9 +123,9 @@ def test_fp32_coefficients_match_fp64_oracle(cqr, sid, n, pr, K, b, storage, kin
         Gh = oc.kron_generator(oc.r_generator(gh, lay.storage), lay.bw)
         d_r = np.linalg.norm(Rg[:, n:] - Rg[:, :n] @ Gh) / np.linalg.norm(Rg[:, n:])
         carried = np.linalg.norm(Qg[:, n:]) / np.linalg.norm(Rg[:, n:])
-        print(f"    R-checksum relation {d_r:.2e}, carried residual {carried:.2e}, "
-              f"bound {r_relation_bound(n):.2e}", flush=True)
-        assert d_r <= r_relation_bound(n) and carried <= r_relation_bound(n)
+        bound = r_relation_bound(n, precision)
+        print(f"    R-checksum relation {d_r:.2e}, carried residual {carried:.2e}, bound {bound:.2e}", flush=True)
+        assert d_r <= bound and carried <= bound
     if kind == "gauss":
         assert rel(Rg[:, :n], ref["R"][:, :n]) <= 1e-11
         assert rel(Qt, ref["Q"][:, :n]) <= 1e-11
@@ -127,10 +143,11 @@ def _decode_gain(gen: np.ndarray, lost: list[int], chk_lost: list[int]) -> float
     return float(max(ginv, reenc))
 
 
-def test_fp32_coefficients_recover_failures(cqr):
-    n, pr, K, b = 512, 8, 2, 64
+@pytest.mark.parametrize("precision,n,pr,K,b", [("fp32", 512, 8, 2, 64), ("bf16x3", 512, 4, 2, 128)])
+def test_reduced_precision_coefficients_recover_failures(cqr, precision, n, pr, K, b):
+    print(f"[case] mixed {precision} recovery n={n} pr={pr} K={K} b={b}", flush=True)
     A, v, gh, lay = make_inputs(n, pr, K, b, "in", seed=9)
-    q = cqr.CodedQR(gpu_config(cqr, lay, b, precision=cqr.CQR_TRAIL_FP32), v, gh)
+    q = cqr.CodedQR(gpu_config(cqr, lay, b, precision=_code(cqr, precision)), v, gh)
     sched = synth.draw_schedule("random", n // b, pr, pr, 9, nfail=2)
     ghm = oc.r_generator(gh, lay.storage)
     Gh = oc.kron_generator(ghm, lay.bw)
@@ -158,7 +175,7 @@ def test_fp32_coefficients_recover_failures(cqr):
               f"(relation error {d_rel:.2e} x decode gain {gain:.2f})", flush=True)
         assert rel(Qg, before_Q) <= 1e-10
         assert err_r <= 1.01 * gain * d_rel + 1e-12 * np.abs(before_R).max()
-        assert d_rel <= r_relation_bound(n) * chk_norm
+        assert d_rel <= r_relation_bound(n, precision) * chk_norm
     q.factor(At, R, k, n // b)
     torch.cuda.synchronize()
     Qg, Rg = host(At), host(R)
