@@ -463,7 +463,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
-    ap.add_argument("--legs", default="fp64,fp32",
+    ap.add_argument("--legs", default="fp64,fp32,bf16x3",
                     help="comma-separated precision legs timed on the same input and schedule; the first gives "
                          "`value` (fp64: FP64 throughout; fp32: the coefficient product R_bar on FP32 MFMA)")
     ap.add_argument("--seed", type=int, default=0)
