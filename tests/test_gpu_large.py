@@ -102,15 +102,28 @@ def _properties(q, A_dev, At, R):
     gv = torch.tensor(q.generators()[0], device=At.device, dtype=torch.float64)
     bs = m // c.pr
     worst = 0.0
+    # D = G_v Q_1 - Q_2, the drift of the carried checksum rows
+    D = torch.empty((c.kv * bs, n), device=At.device, dtype=torch.float64)
     for kk in range(c.kv):
         want = sum(gv[kk, t] * Q1[t * bs:(t + 1) * bs] for t in range(c.pr))
         got = At[m + kk * bs:m + (kk + 1) * bs, :n]
+        D[kk * bs:(kk + 1) * bs] = want - got
         worst = max(worst, ((got - want).abs().max() / Q1.abs().max()).item())
+        del want
+    # With G_0^T G_0 = I + G_v^T G_v (the post-orthogonalization theorem),
+    # (G_0 Q_1)^T (G_0 Q_1) = Q~^T Q~ + E, E = Q_2^T D + D^T Q_2 + D^T D exactly:
+    # the post-orthogonalized factor's orthogonality differs from Q~'s by E
+    Q2 = At[m:, :n]
+    X = Q2.T @ D
+    X += X.T.clone()
+    X += D.T @ D
+    cross = torch.linalg.norm(X).item()
+    del X, D
     from paper_2311_11943_amd import cqr
     Qp = cqr.col_major(m, n, At.device)
     q.postorth(At, Qp)
     orth_post = torch.linalg.norm(eye - Qp.T @ Qp).item()
-    return res, orth, worst, orth_post
+    return res, orth, worst, orth_post, cross
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
@@ -132,9 +145,11 @@ def test_n16384_properties(precision):
     At, R, (rec_fin, rec_q, rec_r, r_ratio) = _run_checked(q, A_dev, inp["schedule"])
     torch.cuda.synchronize()
     assert q.info() == 0
-    res, orth, chk, orth_post = _properties(q, A_dev, At, R)
+    res, orth, chk, orth_post, cross = _properties(q, A_dev, At, R)
     q.close()
-    print(f"    residual {res:.2e}  orth {orth:.2e}  checksum {chk:.2e}  orth post {orth_post:.2e}", flush=True)
+    print(f"    residual {res:.2e}  orth {orth:.2e}  checksum {chk:.2e}  orth post {orth_post:.2e} "
+          f"(checksum-drift term {cross:.2e})", flush=True)
+    assert orth_post <= orth + cross + 1e-11
     # every column operation is FP64 in both forms: Q~ decodes exactly and
     # the row checksums are carried to FP64 rounding
     assert rec_fin <= 1e-10 and rec_q <= 1e-10
@@ -167,9 +182,10 @@ def test_n32768_properties():
     At, R, (rec_fin, rec_q, rec_r, _) = _run_checked(q, A_dev, inp["schedule"])
     torch.cuda.synchronize()
     assert q.info() == 0
-    res, orth, chk, orth_post = _properties(q, A_dev, At, R)
+    res, orth, chk, orth_post, cross = _properties(q, A_dev, At, R)
     q.close()
-    print(f"    residual {res:.2e}  orth {orth:.2e}  checksum {chk:.2e}  orth post {orth_post:.2e}", flush=True)
+    print(f"    residual {res:.2e}  orth {orth:.2e}  checksum {chk:.2e}  orth post {orth_post:.2e} "
+          f"(checksum-drift term {cross:.2e})", flush=True)
     assert rec_fin <= 1e-10 and rec_q <= 1e-10 and rec_r <= 1e-10
     # With K = 8 in-node checksums and 4 failures per block column, a decode
     # uses 4 of the surviving checksum rows; those it does not use keep values
@@ -178,6 +194,8 @@ def test_n32768_properties():
     # entries), and this adds up over the 7 storms (measured 2.6e-10).  At
     # n = 16384 every checksum row takes part in every decode (K = f = 4) and
     # the relation holds to 1e-12.  Post-orthogonalization inherits the drift
-    # (measured 1.9e-10).
+    # through E (measured 1.9e-10), and its orthogonality is bounded by that
+    # of Q~ plus ||E||_F.
     assert chk <= 1e-9
-    assert res <= 1e-12 and orth <= 1e-11 and orth_post <= 1e-9
+    assert res <= 1e-12 and orth <= 1e-11
+    assert orth_post <= orth + cross + 1e-11

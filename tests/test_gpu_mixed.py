@@ -76,6 +76,8 @@ CASES = [
     # three tile rows (odd): the pair kernel's second half of the last pair is empty
     ("odd_tile_rows", 768, 4, 1, 192, "out", "gauss", 1.0),
     ("ragged", 240, 4, 1, 16, "out", "gauss", 1.0),
+    # depth 320 < 512: one split, so the 128 x 128 products store C directly
+    ("one_split", 256, 4, 1, 128, "out", "gauss", 1.0),
 ]
 
 
