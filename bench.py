@@ -120,20 +120,28 @@ def conditioned_input(n: int, cond: float, seed: int, dev) -> np.ndarray:
     return out
 
 
-def source_hash() -> str:
-    """Hash of the sources the product kernels (the roofline candidates) are built from."""
-    h = hashlib.sha256()
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of one kernel's definition (from its template line to its closing
+    brace) in the library's sources, e.g. kernel = "nnq_kernel<0>"; "" if not
+    found.  A traffic record holds for the kernel text it was measured on."""
+    name = kernel.split("<")[0]
     csrc = os.path.join(ROOT, "paper_2311_11943_amd", "csrc")
-    for name in ("cqr_gemm.hip", "cqr_kernels.hpp"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    for src in sorted(os.listdir(csrc)):
+        if not src.endswith((".hip", ".hpp", ".cpp")):
+            continue
+        with open(os.path.join(csrc, src)) as f:
+            lines = f.read().split("\n")
+        for i, line in enumerate(lines):
+            if f"void {name}(" in line and "__global__" in line:
+                start = i - 1 if i > 0 and lines[i - 1].startswith("template") else i
+                end = next(j for j in range(i, len(lines)) if lines[j] == "}")
+                return hashlib.sha256("\n".join(lines[start:end + 1]).encode()).hexdigest()[:16]
+    return ""
 
 
 def traffic_record(phase: str, workload: str):
     """HBM traffic per launch measured by rocprofv3 counters (profiles/), only
-    if it was taken on the current kernel sources."""
+    if it was taken on the current text of that kernel."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -141,7 +149,7 @@ def traffic_record(phase: str, workload: str):
         rec = json.load(f)
     key = f"{workload}:{phase}"
     r = rec.get(key)
-    if not r or r.get("source_hash") != source_hash():
+    if not r or r.get("source_hash") != kernel_source_hash(r.get("kernel", "")):
         return None
     return r.get("bytes_per_launch")
 

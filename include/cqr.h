@@ -236,6 +236,10 @@ cqr_status coded_qr_erase(cqr_plan plan, double* Q, int64_t ldq, double* R, int6
  * of surviving blocks, written by one HIP pass.
  * Returns CQR_ENOTRECOVERABLE (nothing enqueued) if a line has more erased
  * data blocks than surviving checksums, CQR_ESINGULAR if G_hat is singular.
+ * No panel index is taken: between panels both relations hold for every
+ * column, finished or not, so the decode is the same at any panel boundary;
+ * no workspace either: the decode coefficients travel in the kernel
+ * arguments.
  */
 cqr_status coded_qr_recover(cqr_plan plan, double* Q, int64_t ldq, double* R, int64_t ldr,
                             const int32_t* failed_ij, int32_t nfailed, hipStream_t stream);
