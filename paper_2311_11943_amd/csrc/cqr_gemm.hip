@@ -969,9 +969,9 @@ static int pick_split(int tiles, int64_t K, int64_t cap) {
   return ns;
 }
 
-// The 128 x 128-tile products (two workgroups per CU, 512 slots): about 1280
-// workgroups whatever the tile count, so that the last wave of workgroups is
-// short, each split keeping at least 256 rows.  Alone, the 128 x 20480
+// The 512-thread products (128 x 128 or two-tile-row; two workgroups per CU,
+// 512 slots): about 1280 workgroups whatever the tile count, so that the last
+// wave of workgroups is short, each split keeping at least 256 rows.  Alone, the 128 x 20480
 // product of depth 24576 (160 tiles) runs at 60.8 TFLOP/s with 8 splits
 // against 51.5 with the 3 that filling one wave of slots gives.
 static int pick_split_quad(int blocks, int64_t K, int64_t cap, int tiles) {
@@ -1001,7 +1001,7 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   // the split count fills the grid of workgroups the product launches
   const int blocks = quad || bf3 ? (tilesM + 1) / 2 * ((tilesN + 1) / 2) : pair ? (tilesM + 1) / 2 * tilesN : tiles;
   int ns = force_split > 0 ? force_split
-           : quad || bf3   ? pick_split_quad(blocks, K, s.npart, tiles)
+           : quad || bf3 || pair ? pick_split_quad(blocks, K, s.npart, tiles)
                            : pick_split(blocks, K, s.npart);
   while (ns > 1 && (int64_t)ns * tiles > s.npart) --ns;
   int64_t kchunk = (K + ns - 1) / ns;
