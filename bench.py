@@ -292,7 +292,7 @@ def run_adjoint(args):
     from paper_2311_11943_amd import autograd as ag
     from paper_2311_11943_amd import cqr
     dev = torch.device("cuda:0")
-    prec = cqr.CQR_TRAIL_FP32 if args.precision == "fp32" else cqr.CQR_FP64
+    prec = PRECISIONS[args.precision]["code"]
     if args.adjoint_workload == "c5":
         w = WORKLOADS["c5"]
         m = n = w["n"]
@@ -379,7 +379,7 @@ def run_adjoint(args):
     print(json.dumps({
         "metric": "coded-QR least-squares forward + adjoint time", "value": round(fm + bm, 4), "unit": "ms",
         "higher_is_better": False, "steps": args.steps, "warmup": args.warmup,
-        "dtype": "f64" if args.precision == "fp64" else "f32 trailing update / f64 (adjoint f64)",
+        "dtype": PRECISIONS[args.precision]["dtype"] + ("" if args.precision == "fp64" else " (adjoint f64)"),
         "data": "synthetic",
         "config": {"workload": desc, "m": m, "n": n, "grid": grid, "b": b, "K": K, "precision": args.precision,
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched]},
@@ -483,8 +483,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, launch one plain copy kernel of 512 MiB (y = 2x) as the reference for "
                          "HBM byte counters")
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"),
-                    help="--adjoint only: fp32 runs the forward's coefficient products on FP32 MFMA")
+    ap.add_argument("--precision", default="fp64", choices=tuple(PRECISIONS),
+                    help="--adjoint only: the forward's coefficient products in this precision (the adjoint is FP64)")
     ap.add_argument("--cond", type=float, default=0.0,
                     help="> 0: A = U diag(s) V^T with Haar U, V and log-spaced s of this condition number "
                          "instead of a Gaussian A")
