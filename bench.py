@@ -317,7 +317,7 @@ def run_adjoint(args):
     xt = torch.tensor(synth.gaussian(n, 1, args.seed + 2), device=dev)
 
     def fwd():
-        Q, R1 = ag.coded_qr(A, engine, sched)
+        Q, R1 = ag.coded_qr(A, engine, sched, recompute=args.recompute)
         return ag.coded_solve(Q, R1, B, engine)
 
     def ev():
@@ -382,6 +382,7 @@ def run_adjoint(args):
         "dtype": PRECISIONS[args.precision]["dtype"] + ("" if args.precision == "fp64" else " (adjoint f64)"),
         "data": "synthetic",
         "config": {"workload": desc, "m": m, "n": n, "grid": grid, "b": b, "K": K, "precision": args.precision,
+                   "recompute": args.recompute,
                    "failure_schedule": [[t, [list(x) for x in nodes]] for t, nodes in sched]},
         "forward_ms": round(fm, 4), "backward_ms": round(bm, 4),
         "forward_tflops": round(f_fl / (fm * 1e-3) / 1e12, 3), "backward_tflops": round(b_fl / (bm * 1e-3) / 1e12, 3),
@@ -501,6 +502,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the benchmark line: forward + adjoint of a least-squares loss through the coded "
                          "QR and the coded solve, one JSON line")
+    ap.add_argument("--recompute", action="store_true",
+                    help="--adjoint: keep only A for the backward and factor again there")
     ap.add_argument("--adjoint-workload", default="c4", choices=("c4", "c5"),
                     help="--adjoint: c4 (m = 65536, n = 512, 16 x 1 grid) or c5 (n = 32768, 16 x 16 grid)")
     ap.add_argument("--reps", type=int, default=0,

@@ -11,6 +11,12 @@ reads.
     Q, R1 = coded_qr(A, engine, schedule)   # Q = Q~[:, :n] (m' x n), R1 (n x n)
     x = coded_solve(Q, R1, b, engine)       # R_1^{-1} (G_0 Q_1)^T (G_0 b)
     ((x - x_target) ** 2).sum().backward()  # A.grad, b.grad
+
+With coded_qr(A, engine, schedule, recompute=True) the forward keeps only A
+for the backward and the backward runs the factorization again (it is
+deterministic: every reduction sums in a fixed order), trading one more
+forward for the m' x N encoded matrix that would otherwise stay alive
+between the passes.
 """
 from __future__ import annotations
 
@@ -27,34 +33,52 @@ def _colmajor(t: torch.Tensor, rows: int, cols: int, device) -> torch.Tensor:
     return out
 
 
+def _factor(A, engine, schedule):
+    """Encode A and factor it with the schedule's erasures and recoveries;
+    returns the encoded matrix and R."""
+    c = engine.cfg
+    At, R = engine.alloc()
+    At[:c.m, :c.n].copy_(A)
+    engine.encode(At)
+    k = 0
+    for t, nodes in list(schedule) + [(c.npanels, None)]:
+        engine.factor(At, R, k, t)
+        k = t
+        if nodes is None:
+            break
+        engine.erase(At, R, nodes)
+        engine.recover(At, R, nodes)
+    return At, R
+
+
 class CodedQRFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, A, engine, schedule):
+    def forward(ctx, A, engine, schedule, recompute):
         c = engine.cfg
-        At, R = engine.alloc()
-        At[:c.m, :c.n].copy_(A)
-        engine.encode(At)
-        k = 0
-        for t, nodes in list(schedule) + [(c.npanels, None)]:
-            engine.factor(At, R, k, t)
-            k = t
-            if nodes is None:
-                break
-            engine.erase(At, R, nodes)
-            engine.recover(At, R, nodes)
+        At, R = _factor(A, engine, schedule)
         Q, R1 = At[:, :c.n], R[:c.n, :c.n]
         ctx.engine = engine
-        ctx.save_for_backward(Q, R1)
+        ctx.schedule = schedule
+        ctx.recompute = recompute
+        if recompute:
+            ctx.save_for_backward(A)
+        else:
+            ctx.save_for_backward(Q, R1)
         return Q, R1
 
     @staticmethod
     def backward(ctx, dQ, dR):
         engine = ctx.engine
         c = engine.cfg
-        Q, R1 = ctx.saved_tensors
+        if ctx.recompute:
+            (A,) = ctx.saved_tensors
+            At, R = _factor(A, engine, ctx.schedule)
+            Q, R1 = At[:, :c.n], R[:c.n, :c.n]
+        else:
+            Q, R1 = ctx.saved_tensors
         dQ = _colmajor(dQ, c.mp, c.n, Q.device)
         dR = _colmajor(dR, c.n, c.n, Q.device)
-        return engine.backward(Q, R1, dQ, dR), None, None
+        return engine.backward(Q, R1, dQ, dR), None, None, None
 
 
 class CodedSolveFunction(torch.autograd.Function):
@@ -79,9 +103,10 @@ class CodedSolveFunction(torch.autograd.Function):
         return dQ, dR, dB, None
 
 
-def coded_qr(A: torch.Tensor, engine: "cqr.CodedQR", schedule=()):
-    """(Q~[:, :n], R_1) of the coded QR of A (m x n, FP64, on the engine's device)."""
-    return CodedQRFunction.apply(A, engine, list(schedule))
+def coded_qr(A: torch.Tensor, engine: "cqr.CodedQR", schedule=(), recompute: bool = False):
+    """(Q~[:, :n], R_1) of the coded QR of A (m x n, FP64, on the engine's device).
+    recompute: keep only A for the backward and factor again there."""
+    return CodedQRFunction.apply(A, engine, list(schedule), bool(recompute))
 
 
 def coded_solve(Q: torch.Tensor, R1: torch.Tensor, B: torch.Tensor, engine: "cqr.CodedQR") -> torch.Tensor:

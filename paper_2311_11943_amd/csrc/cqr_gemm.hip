@@ -440,12 +440,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // of B's column lc.  Each wave stores its 32 x 32 quadrant of its own 64 x 64
 // tile with the contract of tn_lds_kernel (a missing second tile row of an
 // odd tilesM stages and computes but stores nothing).
-// Taken by products with at least two tile rows and four tile columns (the
-// trailing products of panels wider than 64 columns, in FP64 and FP32, the
-// re-projections of 256-column panels): alone, the K = 49152, 256 x 32768
-// FP64 product runs at 63 TFLOP/s against 55 for tn_lds_kernel, and the
-// 128 x 20480 product with depth 24576 at 55 against 52 (each with the split
-// count that fills its grid).
+// Taken by FP32 products with at least two tile rows and four tile columns
+// (the mixed-precision trailing products of panels wider than 64 columns),
+// and by FP64 ones of that shape that tnq_kernel does not take (a depth that
+// is not a multiple of 16).  Alone, the K = 49152, 256 x 32768 FP64 product
+// ran at 63 TFLOP/s on it against 55 for tn_lds_kernel (tnq_kernel: 65-67).
 template <int TAG, bool F32>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void tn2_kernel(TnArgs a) {
   constexpr int SK = 16, LW = SK + 2;

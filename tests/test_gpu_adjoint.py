@@ -120,3 +120,29 @@ def test_gradcheck_small(mods):
 
     assert torch.autograd.gradcheck(f, (At, Bt), eps=1e-6, atol=1e-6, rtol=1e-4)
     engine.close()
+
+
+def test_recomputed_factorization_gives_the_same_gradient(mods):
+    """coded_qr(..., recompute=True) keeps only A and factors again in the
+    backward; the factorization is deterministic, so the gradients are
+    bitwise those of the stored-factor path."""
+    cqr, ag = mods
+    A, v, gh, lay = make_inputs(256, 8, 2, 32, "in", seed=37)
+    b = 32
+    sched = synth.draw_schedule("random", lay.n // b, lay.pr, lay.pc, 37, nfail=2)
+    print(f"[case] recompute, schedule {sched}", flush=True)
+    Bh = synth.gaussian(lay.m, 1, 38)
+    xt = torch.tensor(synth.gaussian(lay.n, 1, 39), device="cuda:0")
+    engine = cqr.CodedQR(gpu_config(cqr, lay, b), v, gh)
+    grads = []
+    for recompute in (False, True):
+        At = torch.tensor(A, device="cuda:0", requires_grad=True)
+        Bt = torch.tensor(Bh, device="cuda:0", requires_grad=True)
+        Q, R1 = ag.coded_qr(At, engine, sched, recompute=recompute)
+        x = ag.coded_solve(Q, R1, Bt, engine)
+        del Q
+        ((x - xt) ** 2).sum().backward()
+        torch.cuda.synchronize()
+        grads.append((host(At.grad), host(Bt.grad)))
+    engine.close()
+    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
