@@ -35,7 +35,7 @@ struct cqr_plan_s {
   int64_t npart = 0, nS = 0;
   int64_t ldx = 0, xstride = 0;   // first-pass panel copies for the early update (0: none)
   size_t off_part = 0, off_part2 = 0, off_S = 0, off_G = 0, off_T = 0, off_R1 = 0, off_X = 0, off_T2 = 0,
-         ws_bytes = 0;
+         off_colw = 0, ws_bytes = 0;
   int ninfo = 0;           // ints of the info area: 64 status words, then one fallback flag per panel
   double eta = 0.0;        // ICGS threshold in use
   // lookahead: the panel chain's stream, the update stream and four events,
@@ -222,6 +222,7 @@ cqr::Scratch scratch_of(const cqr_plan_s& p, void* ws, bool second = false) {
   s.ldx = p.ldx;
   s.xstride = p.xstride;
   s.T2 = reinterpret_cast<double*>(b + p.off_T2);
+  s.colw = reinterpret_cast<double*>(b + p.off_colw);
   return s;
 }
 
@@ -380,10 +381,11 @@ void chol(cqr_plan_s& p, const double* W, int64_t ldw, int w, int pass, double* 
        [&] { cqr::launch_chol(W, ldw, w, pass, Rout, ldr, X, ldx, Rbar, panel, s, st, Tcopy, P, ldp, p.mp, fb); });
 }
 
-// Column-wise panel modes (CGS2, ICGS, MGS): one workgroup orthogonalises the
-// leaf P (m' x w) and stores R[leaf, leaf].  Flops: 4 m' w^2 for CGS2 (two
-// projections, each a product and an update), 2 m' w^2 for MGS; bytes: the
-// panel read and written once (the minimum).
+// Column-wise panel modes (CGS2, ICGS, MGS): a grid of workgroups
+// orthogonalises the leaf P (m' x w) column by column, one launch per step,
+// and stores R[leaf, leaf].  Flops: 4 m' w^2 for CGS2 (two projections, each
+// a product and an update), 2 m' w^2 for MGS; bytes: the panel read and
+// written once (the minimum).
 void colpanel(cqr_plan_s& p, double* P, int64_t ldq, int w, double* Rout, int64_t ldr, int panel,
               const cqr::Scratch& s, hipStream_t st) {
   cqr::ColArgs a{};
@@ -392,6 +394,7 @@ void colpanel(cqr_plan_s& p, double* P, int64_t ldq, int w, double* Rout, int64_
                                          : (p.cfg.panel == CQR_PANEL_ICGS ? cqr::COLWISE_ICGS : cqr::COLWISE_CGS2);
   a.eta = p.eta;
   a.Rout = Rout; a.ldr = ldr; a.info = s.info; a.panel = panel;
+  a.work = s.colw;
   const double mult = a.mode == cqr::COLWISE_MGS ? 2.0 : 4.0;
   prof(p, PH_COLPANEL, mult * (double)p.mp * w * w, 16.0 * (double)p.mp * w, st,
        [&] { cqr::launch_colpanel(a, st); });
@@ -601,6 +604,7 @@ cqr_status coded_qr_plan_create(const cqr_config* cfg, const double* v_tilde, co
   p->off_T = off;    off = align256(off + sizeof(double) * kLeaf * kLeaf);
   p->off_R1 = off;   off = align256(off + sizeof(double) * kLeaf * kLeaf);
   p->off_T2 = off;   off = align256(off + sizeof(double) * kLeaf * kLeaf);
+  p->off_colw = off; off = align256(off + sizeof(double) * (size_t)cqr::kColWorkDoubles);
   if (b <= kLeaf) {
     // two copies of a first-pass panel (even leading dimension, 256-byte
     // aligned each) for the update that starts before the second pass

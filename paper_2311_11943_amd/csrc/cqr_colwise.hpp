@@ -16,8 +16,10 @@
 // waves in LDS, so results do not depend on scheduling.  Normalisation of
 // column j is folded into the first pass of column j + 1.
 //
-// Used by colpanel_kernel (the CGS2 / ICGS / MGS panel modes) and by the
-// second Cholesky-QR pass when a Cholesky factorization breaks down.
+// colwise_panel is the second Cholesky-QR pass's fallback when a Cholesky
+// factorization breaks down (one workgroup, column-wise CGS2);
+// colwise_block_sum also serves colgrid_kernel, the multi-workgroup form of
+// the CGS2 / ICGS / MGS panel modes.
 #pragma once
 #include "cqr_kernels.hpp"
 

@@ -1577,22 +1577,258 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
   chol_body<false>(a, Rl, Tl, prow, dg, flags, &L);
 }
 
-// One workgroup orthogonalises a panel leaf column by column (the CGS2, ICGS
-// and MGS panel modes) and stores its R block.
-__global__ __launch_bounds__(512) void colpanel_kernel(ColArgs a) {
+// A panel leaf orthogonalised column by column (the CGS2, ICGS and MGS panel
+// modes) by a grid of workgroups, each owning one slab of rows.  A column
+// needs a sum over all rows before every update, so each step of the method
+// is one launch: it first reduces the partial sums every workgroup of the
+// previous launch left (all workgroups sum them redundantly, in the same
+// fixed order, so they take identical decisions), then works on its own
+// slab and leaves its partial sums for the next launch.  Kernel boundaries
+// order the steps; nothing waits inside a launch.
+//
+// CGS2 / ICGS, column j:
+//   PROJECT(j)  s1 = the reduced P[:, <j]^T p_j; column j-1 normalised by its
+//               r (known now); p_j -= P[:, <j] s1; partials of ||p_j||^2 and,
+//               speculatively, of P[:, <j]^T p_j for a second projection.
+//   REORTH(j)   second projection when CGS2, or when ICGS finds
+//               ||p_j||^2 < eta^2 ||p_j before||^2 (the DGKS test); partials
+//               of ||p_j||^2, of ||p_{j+1}||^2 and of P[:, <=j]^T p_{j+1}
+//               (column j not yet normalised: that product is divided by
+//               r_jj in PROJECT(j+1)).
+// MGS, column i (the paper's sequential MGS):
+//   MGS(i)      r_{i-1,i-1} and r_{i-1,c} = u_{i-1}^T u_c / r_{i-1,i-1} from
+//               the reduced sums; q_{i-1} = u_{i-1} / r_{i-1,i-1};
+//               u_c -= r_{i-1,c} q_{i-1} for c >= i; partials of ||u_i||^2 and
+//               of u_i^T u_c for c > i.
+// FINISH normalises the last column.  Workgroup 0 writes R.
+enum : int { CG_START = 0, CG_PROJECT = 1, CG_REORTH = 2, CG_FINISH = 3, CG_MGS = 4 };
+constexpr int kColThreads = 256;
+constexpr int kSlotNA = 64, kSlotNB = 65, kSlotNC = 66;
+
+__global__ __launch_bounds__(kColThreads) void colgrid_kernel(ColArgs a, int G, int64_t rb, int kind, int j,
+                                                              int par) {
   __builtin_amdgcn_s_setprio(2);   // panel chain
-  __shared__ double Rl[kLeaf][kLeaf + 1];
-  __shared__ ColwiseLds<512> L;
-  const bool ok = colwise_panel<512>(a.P, a.ldp, a.mrows, a.w, a.mode, a.eta, Rl, L);
-  for (int e = threadIdx.x; e < a.w * a.w; e += 512) {
-    const int i = e % a.w, j = e / a.w;
-    a.Rout[i + (int64_t)j * a.ldr] = Rl[i][j];
+  __shared__ double red[kColSlots];
+  __shared__ double tmp[3][kColSlots];
+  __shared__ double wred[kColThreads / 64][kColChunk + 1];
+  __shared__ double coef[kLeaf + kColChunk];
+  const int tid = threadIdx.x, g = blockIdx.x, w = a.w;
+  const int64_t ld = a.ldp;
+  double* const P = a.P;
+  const int64_t r0 = (int64_t)g * rb, r1 = min(a.mrows, r0 + rb);
+  const int64_t bufsz = (int64_t)kColGridMax * kColSlots;
+  const double* in = a.work + (par ^ 1) * bufsz;
+  double* out = a.work + par * bufsz + (int64_t)g * kColSlots;
+  double* state = a.work + 2 * bufsz;   // [0] ||p_j||^2 before its first projection, [1] after it, [2] second taken
+  const bool lead = g == 0 && tid == 0;
+  const bool first = kind == CG_START || (kind == CG_MGS && j == 0);
+  if (!first) {
+    if (tid < 3 * kColSlots) {
+      const int sl = tid % kColSlots, q = tid / kColSlots;
+      double acc = 0.0;
+      for (int h = q; h < G; h += 3) acc += in[(int64_t)h * kColSlots + sl];
+      tmp[q][sl] = acc;
+    }
+    __syncthreads();
+    if (tid < kColSlots) red[tid] = (tmp[0][tid] + tmp[1][tid]) + tmp[2][tid];
   }
-  if (threadIdx.x == 0 && !ok && a.info[0] == 0) a.info[0] = 1 + a.panel;
+  for (int c = tid; c < kLeaf + kColChunk; c += kColThreads) coef[c] = 0.0;
+  __syncthreads();
+  // r from a squared norm; a zero or non-finite norm flags the panel as
+  // exactly rank-deficient and leaves the column unnormalised
+  auto diag = [&](double r2) {
+    if (!(r2 > 0.0) || !isfinite(r2)) {
+      if (lead && a.info[0] == 0) a.info[0] = 1 + a.panel;
+      r2 = 1.0;
+    }
+    return sqrt(r2);
+  };
+  double acc[kColChunk];
+
+  if (kind == CG_START) {
+    // ||p_0||^2
+    double n = 0.0;
+    for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+      const double y = P[r];
+      n += y * y;
+    }
+#pragma unroll
+    for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
+    colwise_block_sum<kColThreads>(acc, n, 0, out, out + kSlotNA, wred);
+    return;
+  }
+
+  if (kind == CG_PROJECT) {
+    double inv = 1.0;
+    if (j > 0) {
+      const double r = diag(state[2] != 0.0 ? red[kSlotNC] : state[1]);
+      inv = 1.0 / r;
+      if (lead) a.Rout[(j - 1) + (int64_t)(j - 1) * a.ldr] = r;
+    }
+    if (tid < j) coef[tid] = tid == j - 1 ? red[tid] * inv : red[tid];
+    __syncthreads();
+    if (g == 0) {
+      if (tid < j) a.Rout[tid + (int64_t)j * a.ldr] = coef[tid];
+      if (tid == 0) state[0] = red[kSlotNA];
+    }
+    // p_j -= P[:, <j] s1 (column j-1 normalised on the way), ||p_j||^2
+    double n = 0.0;
+    for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+      double x = P[r + j * ld];
+      for (int c0 = 0; c0 < j; c0 += kColChunk) {
+        double v[kColChunk];
+#pragma unroll
+        for (int c = 0; c < kColChunk; ++c) v[c] = c0 + c < j ? P[r + (c0 + c) * ld] : 0.0;
+#pragma unroll
+        for (int c = 0; c < kColChunk; ++c)
+          if (c0 + c == j - 1) {
+            v[c] *= inv;
+            P[r + (j - 1) * ld] = v[c];
+          }
+#pragma unroll
+        for (int c = 0; c < kColChunk; ++c) x -= v[c] * coef[c0 + c];
+      }
+      P[r + j * ld] = x;
+      n += x * x;
+    }
+    // P[:, <j]^T p_j for a second projection
+    for (int c0 = 0; c0 < max(j, 1); c0 += kColChunk) {
+#pragma unroll
+      for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
+      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+        const double x = P[r + j * ld];
+#pragma unroll
+        for (int c = 0; c < kColChunk; ++c)
+          if (c0 + c < j) acc[c] += P[r + (c0 + c) * ld] * x;
+      }
+      colwise_block_sum<kColThreads>(acc, n, max(0, min(kColChunk, j - c0)), out + c0,
+                                     c0 == 0 ? out + kSlotNB : nullptr, wred);
+    }
+    return;
+  }
+
+  if (kind == CG_REORTH) {
+    const double n1 = red[kSlotNB];
+    const bool second = j > 0 && (a.mode == COLWISE_CGS2 || n1 < a.eta * a.eta * state[0]);
+    if (second && tid < j) coef[tid] = red[tid];
+    __syncthreads();
+    if (g == 0) {
+      if (second && tid < j) a.Rout[tid + (int64_t)j * a.ldr] += coef[tid];
+      if (tid == 0) {
+        state[1] = n1;
+        state[2] = second ? 1.0 : 0.0;
+      }
+    }
+    double nc = 0.0;
+    if (second) {
+      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+        double x = P[r + j * ld];
+        for (int c0 = 0; c0 < j; c0 += kColChunk) {
+          double v[kColChunk];
+#pragma unroll
+          for (int c = 0; c < kColChunk; ++c) v[c] = c0 + c < j ? P[r + (c0 + c) * ld] : 0.0;
+#pragma unroll
+          for (int c = 0; c < kColChunk; ++c) x -= v[c] * coef[c0 + c];
+        }
+        P[r + j * ld] = x;
+        nc += x * x;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
+    colwise_block_sum<kColThreads>(acc, nc, 0, out, out + kSlotNC, wred);
+    // the next column's first projection: P[:, <=j]^T p_{j+1}, ||p_{j+1}||^2
+    const int nd = j + 1 < w ? j + 1 : 0;
+    double na = 0.0;
+    for (int c0 = 0; c0 < max(nd, 1); c0 += kColChunk) {
+#pragma unroll
+      for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
+      if (nd > 0) {
+        for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+          const double y = P[r + (j + 1) * ld];
+          if (c0 == 0) na += y * y;
+#pragma unroll
+          for (int c = 0; c < kColChunk; ++c)
+            if (c0 + c < nd) acc[c] += P[r + (c0 + c) * ld] * y;
+        }
+      }
+      colwise_block_sum<kColThreads>(acc, na, max(0, min(kColChunk, nd - c0)), out + c0,
+                                     c0 == 0 ? out + kSlotNA : nullptr, wred);
+    }
+    return;
+  }
+
+  if (kind == CG_MGS) {
+    const int i = j;
+    double inv = 1.0;
+    if (i > 0) {
+      const double r = diag(red[kSlotNA]);
+      inv = 1.0 / r;
+      if (tid >= i && tid < w) coef[tid] = red[tid] * inv;
+      if (lead) a.Rout[(i - 1) + (int64_t)(i - 1) * a.ldr] = r;
+    }
+    __syncthreads();
+    if (g == 0 && i > 0 && tid >= i && tid < w) a.Rout[(i - 1) + (int64_t)tid * a.ldr] = coef[tid];
+    // q_{i-1} = u_{i-1} / r; u_c -= r_{i-1,c} q_{i-1} for c >= i
+    if (i > 0) {
+      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+        const double q = P[r + (i - 1) * ld] * inv;
+        P[r + (i - 1) * ld] = q;
+        for (int c = i; c < w; ++c) P[r + c * ld] -= coef[c] * q;
+      }
+    }
+    // ||u_i||^2 and u_i^T u_c for c > i
+    const int lo = i + 1, nd = w - lo;
+    double na = 0.0;
+    for (int k0 = 0; k0 < max(nd, 1); k0 += kColChunk) {
+#pragma unroll
+      for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
+      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
+        const double u = P[r + i * ld];
+        if (k0 == 0) na += u * u;
+#pragma unroll
+        for (int c = 0; c < kColChunk; ++c)
+          if (k0 + c < nd) acc[c] += P[r + (lo + k0 + c) * ld] * u;
+      }
+      colwise_block_sum<kColThreads>(acc, na, max(0, min(kColChunk, nd - k0)), out + lo + k0,
+                                     k0 == 0 ? out + kSlotNA : nullptr, wred);
+    }
+    return;
+  }
+
+  // CG_FINISH: r of the last column, which is normalised; zeros below R's diagonal
+  const double r = diag(a.mode == COLWISE_MGS ? red[kSlotNA] : (state[2] != 0.0 ? red[kSlotNC] : state[1]));
+  const double inv = 1.0 / r;
+  if (lead) a.Rout[(w - 1) + (int64_t)(w - 1) * a.ldr] = r;
+  if (g == 0)
+    for (int e = tid; e < w * w; e += kColThreads) {
+      const int i = e % w, c = e / w;
+      if (i > c) a.Rout[i + (int64_t)c * a.ldr] = 0.0;
+    }
+  for (int64_t r = r0 + tid; r < r1; r += kColThreads) P[r + (w - 1) * ld] *= inv;
 }
 
+// The launches of one leaf: 2w + 2 for CGS2 / ICGS, w + 1 for MGS.  The slab
+// height keeps a workgroup at one or more rows per thread, on at most
+// kColGridMax workgroups.
 void launch_colpanel(const ColArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(colpanel_kernel, dim3(1), dim3(512), 0, st, a);
+  const int G = (int)std::min<int64_t>(kColGridMax, std::max<int64_t>(1, (a.mrows + kColThreads - 1) / kColThreads));
+  const int64_t rb = (a.mrows + G - 1) / G;
+  int par = 0;
+  auto go = [&](int kind, int j) {
+    hipLaunchKernelGGL(colgrid_kernel, dim3(G), dim3(kColThreads), 0, st, a, G, rb, kind, j, par);
+    par ^= 1;
+  };
+  if (a.mode == COLWISE_MGS) {
+    for (int i = 0; i < a.w; ++i) go(CG_MGS, i);
+  } else {
+    go(CG_START, 0);
+    for (int j = 0; j < a.w; ++j) {
+      go(CG_PROJECT, j);
+      go(CG_REORTH, j);
+    }
+  }
+  go(CG_FINISH, a.w - 1);
 }
 
 CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,

@@ -76,6 +76,7 @@ struct Scratch {
   double* X;          // two first-pass panel copies (ldx x b each, xstride doubles apart)
   int64_t ldx, xstride;
   double* T2;         // the second pass's inverse factor, kept for the update stream
+  double* colw;       // column-wise panel partial sums (kColWorkDoubles)
 };
 
 // Kernel-instance tags: each use of a product kernel gets its own symbol, so
@@ -156,14 +157,22 @@ struct CholArgs {
   int* fb;                          // pass 2, optional: set to 1 when the fallback ran
 };
 
-// One panel leaf orthogonalised column by column (colpanel_kernel).
+// One panel leaf orthogonalised column by column (colgrid_kernel): the rows
+// are split over up to kColGridMax workgroups, and each launch takes one step
+// of the method on every slab, leaving per-workgroup partial sums (kColSlots
+// each) that every workgroup of the next launch reduces in the same order.
 enum : int { COLWISE_CGS2 = 0, COLWISE_ICGS = 1, COLWISE_MGS = 2 };
+constexpr int kColGridMax = 128;
+constexpr int kColSlots = 68;       // 64 inner products, three squared norms, one spare
+// partial sums (two buffers, alternating by launch) and four state words
+constexpr int64_t kColWorkDoubles = 2 * (int64_t)kColGridMax * kColSlots + 4;
 struct ColArgs {
   double* P; int64_t ldp; int64_t mrows;
   int w, mode;                      // w <= kLeaf; mode: COLWISE_CGS2 / _ICGS / _MGS
   double eta;                       // ICGS: reorthogonalise when ||p after|| < eta ||p before||
   double* Rout; int64_t ldr;        // the panel's R block (w x w, zeros below the diagonal)
   int* info; int panel;             // a zero column sets info[0] = 1 + panel
+  double* work;                     // kColWorkDoubles of scratch
 };
 void launch_colpanel(const ColArgs& a, hipStream_t st);
 

@@ -3,8 +3,9 @@
 - Column-wise CGS2, ICGS (DGKS test, eta = 1/sqrt 2) and MGS panels
   (CQR_PANEL_CGS2 / ICGS / MGS) against the oracle's panel of the same name:
   R and Q~ element by element (1e-11 of the largest entry), FP64 residual and
-  orthogonality (1e-12), with and without failures, and the paper's method
-  (MGS panel, no re-projection) at the n = 4096 workload's shape.
+  orthogonality (1e-12), with and without failures, on a tall panel whose
+  leaves take the kernel's widest grid (a ragged last slab), and the paper's
+  method (MGS panel, no re-projection) at the n = 4096 workload's shape.
 - A panel with two nearly dependent columns (one 1e-9 from another,
   cond(A) ~ 1e11): the Cholesky-QR panel breaks down and the column-wise
   CGS2 fallback takes the panel; the result is bounded by backward error
@@ -66,6 +67,33 @@ def test_columnwise_panels_match_oracle(cqr, mode, sid, n, pr, K, b, storage):
     print(f"    R {rel(Rg, ref['R']):.2e} Q {rel(Qg, ref['Q']):.2e} {m}", flush=True)
     assert rel(Rg, ref["R"]) <= 1e-11 and rel(Qg, ref["Q"]) <= 1e-11
     assert m["residual"] <= 1e-12 and m["orth_coded"] <= 1e-12
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_columnwise_panels_on_the_widest_grid(cqr, mode):
+    """A tall panel (m' = 50000 rows: 16 x 1 grid of 2500-row blocks, K_v = 4
+    out-of-node, no horizontal code, n = 192, b = 64, one failure) spreads
+    each leaf over the most workgroups the column-wise kernel takes, with a
+    last slab shorter than the others, against the oracle's panel of the same
+    name."""
+    m, n, pr, K, b = 40000, 192, 16, 4, 64
+    A, v, _, lay = make_inputs(n, pr, K, b, "out", seed=3, m=m, pc=1, kh=0)
+    sched = synth.draw_schedule("random", n // b, pr, 1, 3, nfail=1)
+    print(f"[case] panel {mode} m'={lay.mp} n={n}, schedule {sched}", flush=True)
+    q = cqr.CodedQR(gpu_config(cqr, lay, b, panel=MODES[mode]), v, None)
+    At, R, _, _ = q.run(cqr.to_device_colmajor(A, "cuda:0"), sched)
+    torch.cuda.synchronize()
+    assert q.info() == 0
+    Qg, Rg = host(At), host(R)
+    q.close()
+    ref = oc.run(oc.Problem(A, lay, v, None, oc.FactorOptions(b, mode), sched))
+    # R's own checksum rows follow its n rows (the oracle returns R_1's rows)
+    Rg = Rg[:n]
+    res = np.linalg.norm(A - Qg[:m, :n] @ Rg[:n, :n]) / np.linalg.norm(A)
+    orth = np.linalg.norm(np.eye(n) - Qg[:, :n].T @ Qg[:, :n])
+    print(f"    R {rel(Rg, ref['R']):.2e} Q {rel(Qg, ref['Q']):.2e} residual {res:.2e} orth {orth:.2e}", flush=True)
+    assert rel(Rg, ref["R"]) <= 1e-11 and rel(Qg, ref["Q"]) <= 1e-11
+    assert res <= 1e-12 and orth <= 1e-12
 
 
 def test_paper_method_mgs_without_reprojection(cqr):
