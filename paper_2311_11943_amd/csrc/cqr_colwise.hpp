@@ -18,7 +18,7 @@
 //
 // colwise_panel is the second Cholesky-QR pass's fallback when a Cholesky
 // factorization breaks down (one workgroup, column-wise CGS2);
-// colwise_block_sum also serves colgrid_kernel, the multi-workgroup form of
+// colwise_wave_sum16 also serves colgrid_kernel, the multi-workgroup form of
 // the CGS2 / ICGS / MGS panel modes.
 #pragma once
 #include "cqr_kernels.hpp"
@@ -36,12 +36,10 @@ struct ColwiseLds {
   double s2[kLeaf + 1];      // second projection's coefficients
 };
 
-// Workgroup sums of v[0..16) into out[0..nv) and of `extra` into *xout (when
-// xout != nullptr).  Every thread calls it.
-template <int NT>
-__device__ __forceinline__ void colwise_block_sum(double (&v)[kColChunk], double extra, int nv, double* out,
-                                                  double* xout, double (*red)[kColChunk + 1]) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// Wavefront sums of v[0..16): afterwards every lane l holds the sum over the
+// wavefront of v[l mod 16] (v is overwritten).
+__device__ __forceinline__ double colwise_wave_sum16(double (&v)[kColChunk]) {
+  const int lane = threadIdx.x & 63;
   // transposing butterfly over lane bits 3..0: a lane keeps the half of its
   // slots whose index bit matches its lane bit and adds the partner's copy,
   // in place (slot c of the kept half moves to slot c of the lower half)
@@ -58,6 +56,16 @@ __device__ __forceinline__ void colwise_block_sum(double (&v)[kColChunk], double
   double x = v[0];
   x += __shfl_xor(x, 16, 64);
   x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+// Workgroup sums of v[0..16) into out[0..nv) and of `extra` into *xout (when
+// xout != nullptr).  Every thread calls it.
+template <int NT>
+__device__ __forceinline__ void colwise_block_sum(double (&v)[kColChunk], double extra, int nv, double* out,
+                                                  double* xout, double (*red)[kColChunk + 1]) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double x = colwise_wave_sum16(v);
   double e = extra;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);

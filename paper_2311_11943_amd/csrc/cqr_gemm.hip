@@ -1601,17 +1601,40 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
 //               u_c -= r_{i-1,c} q_{i-1} for c >= i; partials of ||u_i||^2 and
 //               of u_i^T u_c for c > i.
 // FINISH normalises the last column.  Workgroup 0 writes R.
+//
+// A thread loads the columns a step touches in its row into registers at
+// once, computes the update and the step's inner products from them, and
+// stores what changed; with one row per thread (up to 65536 rows) a launch
+// waits on memory about three times: the previous partial sums, the row, and
+// the stores.  Partial sums: slots [0, 64) inner products (whole 16-slot
+// chunks are written), 64-66 the squared norms (all three written by every
+// launch).
 enum : int { CG_START = 0, CG_PROJECT = 1, CG_REORTH = 2, CG_FINISH = 3, CG_MGS = 4 };
 constexpr int kColThreads = 256;
 constexpr int kSlotNA = 64, kSlotNB = 65, kSlotNC = 66;
 
-__global__ __launch_bounds__(kColThreads) void colgrid_kernel(ColArgs a, int G, int64_t rb, int kind, int j,
-                                                              int par) {
+// Row r's columns [lo, hi) into v (zeros elsewhere) and its columns e0 and
+// e1 (e1 < 0: none) into x0, x1, addressed as a uniform column base plus the
+// row's 32-bit byte offset in the slab that starts at row r0.
+__device__ __forceinline__ void colgrid_load_row(double (&v)[kLeaf], double& x0, double& x1, const double* P,
+                                                 int64_t r0, int64_t ld, int64_t r, bool act, int lo, int hi, int e0,
+                                                 int e1) {
+  const char* const slab = reinterpret_cast<const char*>(P + r0);
+  const uint32_t off = act ? (uint32_t)(r - r0) * 8u : 0u;
+#pragma unroll
+  for (int c = 0; c < kLeaf; ++c)
+    v[c] = (act && c >= lo && c < hi) ? *reinterpret_cast<const double*>(slab + c * ld * 8 + off) : 0.0;
+  x0 = act ? P[r + e0 * ld] : 0.0;
+  x1 = act && e1 >= 0 ? P[r + e1 * ld] : 0.0;
+}
+
+template <int kind>
+__global__ __launch_bounds__(kColThreads) void colgrid_kernel(ColArgs a, int G, int64_t rb, int j, int par) {
   __builtin_amdgcn_s_setprio(2);   // panel chain
   __shared__ double red[kColSlots];
-  __shared__ double tmp[3][kColSlots];
-  __shared__ double wred[kColThreads / 64][kColChunk + 1];
-  __shared__ double coef[kLeaf + kColChunk];
+  __shared__ double tmp[kColThreads];
+  __shared__ double wsum[kColThreads / 64][kLeaf + kColChunk];   // per-wavefront sums of every slot
+  __shared__ double coef[kLeaf + kColChunk];                     // zero beyond the step's coefficients
   const int tid = threadIdx.x, g = blockIdx.x, w = a.w;
   const int64_t ld = a.ldp;
   double* const P = a.P;
@@ -1621,18 +1644,57 @@ __global__ __launch_bounds__(kColThreads) void colgrid_kernel(ColArgs a, int G, 
   double* out = a.work + par * bufsz + (int64_t)g * kColSlots;
   double* state = a.work + 2 * bufsz;   // [0] ||p_j||^2 before its first projection, [1] after it, [2] second taken
   const bool lead = g == 0 && tid == 0;
-  const bool first = kind == CG_START || (kind == CG_MGS && j == 0);
-  if (!first) {
-    if (tid < 3 * kColSlots) {
-      const int sl = tid % kColSlots, q = tid / kColSlots;
+
+  // inner-product slots this launch reads [rlo, rhi) and writes [wlo, whi);
+  // columns a row holds in registers [lo, hi); single columns e0 and e1
+  int rlo = 0, rhi = 0, wlo = 0, whi = 0, lo = 0, hi = 0, e0 = 0, e1 = -1;
+  if constexpr (kind == CG_PROJECT) {   // e0 = p_j, e1 = column j-1
+    rhi = j; whi = j; hi = j; e0 = j; e1 = j - 1;
+  }
+  if constexpr (kind == CG_REORTH) {    // e0 = p_j, e1 = p_{j+1}
+    rhi = j; whi = j + 1 < w ? j + 1 : 0; hi = j; e0 = j; e1 = j + 1 < w ? j + 1 : -1;
+  }
+  if constexpr (kind == CG_MGS) {       // e0 = u_j, e1 = u_{j-1}
+    if (j > 0) { rlo = j; rhi = w; }
+    wlo = j + 1; whi = w; lo = j; hi = w; e0 = j; e1 = j - 1;
+  }
+  if constexpr (kind == CG_FINISH) e0 = w - 1;
+
+  double v[kLeaf], x0 = 0.0, x1 = 0.0;
+  // the first row block is loaded before the reduction below, which it does
+  // not depend on, so the two memory latencies overlap
+  const int nit = (int)((rb + kColThreads - 1) / kColThreads);
+  colgrid_load_row(v, x0, x1, P, r0, ld, r0 + tid, r0 + tid < r1, lo, hi, e0, e1);
+  const double st0 = state[0], st1 = state[1], st2 = state[2];
+
+  for (int c = tid; c < kLeaf + kColChunk; c += kColThreads) coef[c] = 0.0;
+  // reduce the previous launch's partials: its inner products in [rlo, rhi)
+  // and the three norms; thread (si, q) sums workgroups q, q + Q, ... in order
+  if (!(kind == CG_START || (kind == CG_MGS && j == 0))) {
+    const int nd = rhi - rlo, ns = nd + 3, Q = kColThreads / ns;
+    const int si = tid % ns, q = tid / ns;
+    const int slot = si < nd ? rlo + si : kSlotNA + (si - nd);
+    if (q < Q) {
       double acc = 0.0;
-      for (int h = q; h < G; h += 3) acc += in[(int64_t)h * kColSlots + sl];
-      tmp[q][sl] = acc;
+      int h = q;
+      for (; h + 3 * Q < G; h += 4 * Q) {
+        const double y0 = in[(int64_t)h * kColSlots + slot], y1 = in[(int64_t)(h + Q) * kColSlots + slot];
+        const double y2 = in[(int64_t)(h + 2 * Q) * kColSlots + slot], y3 = in[(int64_t)(h + 3 * Q) * kColSlots + slot];
+        acc += y0;
+        acc += y1;
+        acc += y2;
+        acc += y3;
+      }
+      for (; h < G; h += Q) acc += in[(int64_t)h * kColSlots + slot];
+      tmp[q * ns + si] = acc;
     }
     __syncthreads();
-    if (tid < kColSlots) red[tid] = (tmp[0][tid] + tmp[1][tid]) + tmp[2][tid];
+    if (tid < ns) {
+      double s = 0.0;
+      for (int k = 0; k < Q; ++k) s += tmp[k * ns + tid];
+      red[tid < nd ? rlo + tid : kSlotNA + (tid - nd)] = s;
+    }
   }
-  for (int c = tid; c < kLeaf + kColChunk; c += kColThreads) coef[c] = 0.0;
   __syncthreads();
   // r from a squared norm; a zero or non-finite norm flags the panel as
   // exactly rank-deficient and leaves the column unnormalised
@@ -1643,192 +1705,182 @@ __global__ __launch_bounds__(kColThreads) void colgrid_kernel(ColArgs a, int G, 
     }
     return sqrt(r2);
   };
-  double acc[kColChunk];
 
-  if (kind == CG_START) {
-    // ||p_0||^2
-    double n = 0.0;
-    for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-      const double y = P[r];
-      n += y * y;
+  if constexpr (kind == CG_FINISH) {
+    // r of the last column, which is normalised; zeros below R's diagonal
+    const double r = diag(a.mode == COLWISE_MGS ? red[kSlotNA] : (st2 != 0.0 ? red[kSlotNC] : st1));
+    const double inv = 1.0 / r;
+    if (lead) a.Rout[(w - 1) + (int64_t)(w - 1) * a.ldr] = r;
+    if (g == 0)
+      for (int e = tid; e < w * w; e += kColThreads) {
+        const int i = e % w, c = e / w;
+        if (i > c) a.Rout[i + (int64_t)c * a.ldr] = 0.0;
+      }
+    for (int it = 0; it < nit; ++it) {
+      const int64_t r = r0 + (int64_t)it * kColThreads + tid;
+      if (it > 0) colgrid_load_row(v, x0, x1, P, r0, ld, r, r < r1, lo, hi, e0, e1);
+      if (r < r1) P[r + (w - 1) * ld] = x0 * inv;
     }
-#pragma unroll
-    for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
-    colwise_block_sum<kColThreads>(acc, n, 0, out, out + kSlotNA, wred);
-    return;
-  }
-
-  if (kind == CG_PROJECT) {
+  } else {
+    // this step's coefficients, decision and R entries
     double inv = 1.0;
-    if (j > 0) {
-      const double r = diag(state[2] != 0.0 ? red[kSlotNC] : state[1]);
-      inv = 1.0 / r;
-      if (lead) a.Rout[(j - 1) + (int64_t)(j - 1) * a.ldr] = r;
+    bool second = false;
+    if constexpr (kind == CG_PROJECT) {
+      if (j > 0) {
+        const double r = diag(st2 != 0.0 ? red[kSlotNC] : st1);
+        inv = 1.0 / r;
+        if (lead) a.Rout[(j - 1) + (int64_t)(j - 1) * a.ldr] = r;
+      }
+      if (tid < j) coef[tid] = tid == j - 1 ? red[tid] * inv : red[tid];
+      __syncthreads();
+      if (g == 0) {
+        if (tid < j) a.Rout[tid + (int64_t)j * a.ldr] = coef[tid];
+        if (tid == 0) state[0] = red[kSlotNA];
+      }
+    } else if constexpr (kind == CG_REORTH) {
+      const double n1 = red[kSlotNB];
+      second = j > 0 && (a.mode == COLWISE_CGS2 || n1 < a.eta * a.eta * st0);
+      if (second && tid < j) coef[tid] = red[tid];
+      __syncthreads();
+      if (g == 0) {
+        if (second && tid < j) a.Rout[tid + (int64_t)j * a.ldr] += coef[tid];
+        if (tid == 0) {
+          state[1] = n1;
+          state[2] = second ? 1.0 : 0.0;
+        }
+      }
+    } else if constexpr (kind == CG_MGS) {
+      if (j > 0) {
+        const double r = diag(red[kSlotNA]);
+        inv = 1.0 / r;
+        if (tid >= j && tid < w) coef[tid] = red[tid] * inv;
+        if (lead) a.Rout[(j - 1) + (int64_t)(j - 1) * a.ldr] = r;
+      }
+      __syncthreads();
+      if (g == 0 && j > 0 && tid >= j && tid < w) a.Rout[(j - 1) + (int64_t)tid * a.ldr] = coef[tid];
     }
-    if (tid < j) coef[tid] = tid == j - 1 ? red[tid] * inv : red[tid];
-    __syncthreads();
-    if (g == 0) {
-      if (tid < j) a.Rout[tid + (int64_t)j * a.ldr] = coef[tid];
-      if (tid == 0) state[0] = red[kSlotNA];
-    }
-    // p_j -= P[:, <j] s1 (column j-1 normalised on the way), ||p_j||^2
-    double n = 0.0;
-    for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-      double x = P[r + j * ld];
-      for (int c0 = 0; c0 < j; c0 += kColChunk) {
-        double v[kColChunk];
+
+    double total = 0.0;   // threads < kColSlots: this workgroup's sum for slot tid
+    for (int it = 0; it < nit; ++it) {
+      const int64_t r = r0 + (int64_t)it * kColThreads + tid;
+      const bool act = r < r1;
+      if (it > 0) colgrid_load_row(v, x0, x1, P, r0, ld, r, act, lo, hi, e0, e1);
+      double na = 0.0, nb = 0.0, nc = 0.0;
+      if constexpr (kind == CG_START) {
+        na = x0 * x0;
+      } else if constexpr (kind == CG_PROJECT) {
+        // column j-1 normalised; p_j -= P[:, <j] s1; ||p_j||^2; P[:, <j]^T p_j
+        double x = x0;
+        if (j > 0) {
+          const double qp = x1 * inv;
+          if (act) P[r + (j - 1) * ld] = qp;
 #pragma unroll
-        for (int c = 0; c < kColChunk; ++c) v[c] = c0 + c < j ? P[r + (c0 + c) * ld] : 0.0;
+          for (int c = 0; c < kLeaf; ++c)
+            if (c + 1 == j) v[c] = qp;
+        }
 #pragma unroll
-        for (int c = 0; c < kColChunk; ++c)
-          if (c0 + c == j - 1) {
-            v[c] *= inv;
-            P[r + (j - 1) * ld] = v[c];
+        for (int c = 0; c < kLeaf; ++c) x -= v[c] * coef[c];
+        if (act) P[r + j * ld] = x;
+        nb = x * x;
+#pragma unroll
+        for (int c = 0; c < kLeaf; ++c) v[c] *= x;
+      } else if constexpr (kind == CG_REORTH) {
+        double x = x0;
+        const double y = x1;
+        if (second) {
+#pragma unroll
+          for (int c = 0; c < kLeaf; ++c) x -= v[c] * coef[c];
+          if (act) P[r + j * ld] = x;
+          nc = x * x;
+        }
+        // the next column's first projection: P[:, <=j]^T p_{j+1}, ||p_{j+1}||^2
+        na = y * y;
+#pragma unroll
+        for (int c = 0; c < kLeaf; ++c) v[c] = c == j ? x * y : v[c] * y;
+      } else {   // CG_MGS
+        // q_{j-1} = u_{j-1} / r; u_c -= r_{j-1,c} q_{j-1} for c >= j;
+        // ||u_j||^2 and u_j^T u_c for c > j
+        double u = x0;
+        if (j > 0) {
+          const double q = x1 * inv;
+          if (act) P[r + (j - 1) * ld] = q;
+          u -= coef[j] * q;
+          const uint32_t off = act ? (uint32_t)(r - r0) * 8u : 0u;
+          char* const wslab = reinterpret_cast<char*>(P + r0);
+#pragma unroll
+          for (int c = 0; c < kLeaf; ++c) {
+            v[c] -= coef[c] * q;
+            if (act && c >= j && c < w) *reinterpret_cast<double*>(wslab + c * ld * 8 + off) = v[c];
           }
-#pragma unroll
-        for (int c = 0; c < kColChunk; ++c) x -= v[c] * coef[c0 + c];
-      }
-      P[r + j * ld] = x;
-      n += x * x;
-    }
-    // P[:, <j]^T p_j for a second projection
-    for (int c0 = 0; c0 < max(j, 1); c0 += kColChunk) {
-#pragma unroll
-      for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
-      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-        const double x = P[r + j * ld];
-#pragma unroll
-        for (int c = 0; c < kColChunk; ++c)
-          if (c0 + c < j) acc[c] += P[r + (c0 + c) * ld] * x;
-      }
-      colwise_block_sum<kColThreads>(acc, n, max(0, min(kColChunk, j - c0)), out + c0,
-                                     c0 == 0 ? out + kSlotNB : nullptr, wred);
-    }
-    return;
-  }
-
-  if (kind == CG_REORTH) {
-    const double n1 = red[kSlotNB];
-    const bool second = j > 0 && (a.mode == COLWISE_CGS2 || n1 < a.eta * a.eta * state[0]);
-    if (second && tid < j) coef[tid] = red[tid];
-    __syncthreads();
-    if (g == 0) {
-      if (second && tid < j) a.Rout[tid + (int64_t)j * a.ldr] += coef[tid];
-      if (tid == 0) {
-        state[1] = n1;
-        state[2] = second ? 1.0 : 0.0;
-      }
-    }
-    double nc = 0.0;
-    if (second) {
-      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-        double x = P[r + j * ld];
-        for (int c0 = 0; c0 < j; c0 += kColChunk) {
-          double v[kColChunk];
-#pragma unroll
-          for (int c = 0; c < kColChunk; ++c) v[c] = c0 + c < j ? P[r + (c0 + c) * ld] : 0.0;
-#pragma unroll
-          for (int c = 0; c < kColChunk; ++c) x -= v[c] * coef[c0 + c];
         }
-        P[r + j * ld] = x;
-        nc += x * x;
+        na = u * u;
+#pragma unroll
+        for (int c = 0; c < kLeaf; ++c) v[c] *= u;
       }
-    }
+      // workgroup sums of this row block (the chunks covering [wlo, whi),
+      // then the norms): every wavefront butterfly first, independent of one
+      // another, then one exchange through LDS; each slot's total adds the
+      // wavefronts in order, then the row blocks in order
+      double xs[kLeaf / kColChunk + 1];
 #pragma unroll
-    for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
-    colwise_block_sum<kColThreads>(acc, nc, 0, out, out + kSlotNC, wred);
-    // the next column's first projection: P[:, <=j]^T p_{j+1}, ||p_{j+1}||^2
-    const int nd = j + 1 < w ? j + 1 : 0;
-    double na = 0.0;
-    for (int c0 = 0; c0 < max(nd, 1); c0 += kColChunk) {
+      for (int k = 0; k < kLeaf / kColChunk; ++k) {
+        xs[k] = 0.0;
+        if (whi > wlo && (k + 1) * kColChunk > wlo && k * kColChunk < whi) {
+          double v16[kColChunk];
 #pragma unroll
-      for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
-      if (nd > 0) {
-        for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-          const double y = P[r + (j + 1) * ld];
-          if (c0 == 0) na += y * y;
-#pragma unroll
-          for (int c = 0; c < kColChunk; ++c)
-            if (c0 + c < nd) acc[c] += P[r + (c0 + c) * ld] * y;
+          for (int c = 0; c < kColChunk; ++c) v16[c] = v[k * kColChunk + c];
+          xs[k] = colwise_wave_sum16(v16);
         }
       }
-      colwise_block_sum<kColThreads>(acc, na, max(0, min(kColChunk, nd - c0)), out + c0,
-                                     c0 == 0 ? out + kSlotNA : nullptr, wred);
-    }
-    return;
-  }
-
-  if (kind == CG_MGS) {
-    const int i = j;
-    double inv = 1.0;
-    if (i > 0) {
-      const double r = diag(red[kSlotNA]);
-      inv = 1.0 / r;
-      if (tid >= i && tid < w) coef[tid] = red[tid] * inv;
-      if (lead) a.Rout[(i - 1) + (int64_t)(i - 1) * a.ldr] = r;
-    }
-    __syncthreads();
-    if (g == 0 && i > 0 && tid >= i && tid < w) a.Rout[(i - 1) + (int64_t)tid * a.ldr] = coef[tid];
-    // q_{i-1} = u_{i-1} / r; u_c -= r_{i-1,c} q_{i-1} for c >= i
-    if (i > 0) {
-      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-        const double q = P[r + (i - 1) * ld] * inv;
-        P[r + (i - 1) * ld] = q;
-        for (int c = i; c < w; ++c) P[r + c * ld] -= coef[c] * q;
-      }
-    }
-    // ||u_i||^2 and u_i^T u_c for c > i
-    const int lo = i + 1, nd = w - lo;
-    double na = 0.0;
-    for (int k0 = 0; k0 < max(nd, 1); k0 += kColChunk) {
+      {
+        double n16[kColChunk];
 #pragma unroll
-      for (int c = 0; c < kColChunk; ++c) acc[c] = 0.0;
-      for (int64_t r = r0 + tid; r < r1; r += kColThreads) {
-        const double u = P[r + i * ld];
-        if (k0 == 0) na += u * u;
-#pragma unroll
-        for (int c = 0; c < kColChunk; ++c)
-          if (k0 + c < nd) acc[c] += P[r + (lo + k0 + c) * ld] * u;
+        for (int c = 0; c < kColChunk; ++c) n16[c] = 0.0;
+        n16[0] = na;
+        n16[1] = nb;
+        n16[2] = nc;
+        xs[kLeaf / kColChunk] = colwise_wave_sum16(n16);
       }
-      colwise_block_sum<kColThreads>(acc, na, max(0, min(kColChunk, nd - k0)), out + lo + k0,
-                                     k0 == 0 ? out + kSlotNA : nullptr, wred);
+      const int wave = tid >> 6, lane = tid & 63;
+      if (lane < kColChunk) {
+#pragma unroll
+        for (int k = 0; k <= kLeaf / kColChunk; ++k) wsum[wave][k * kColChunk + lane] = xs[k];
+      }
+      __syncthreads();
+      if (tid < kColSlots) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kColThreads / 64; ++q) sacc += wsum[q][tid];
+        total += sacc;
+      }
+      __syncthreads();
     }
-    return;
+    const int k = tid / kColChunk;
+    const bool chunk = whi > wlo && (k + 1) * kColChunk > wlo && k * kColChunk < whi && tid < kLeaf;
+    if (chunk || (tid >= kSlotNA && tid <= kSlotNC)) out[tid] = total;
   }
-
-  // CG_FINISH: r of the last column, which is normalised; zeros below R's diagonal
-  const double r = diag(a.mode == COLWISE_MGS ? red[kSlotNA] : (state[2] != 0.0 ? red[kSlotNC] : state[1]));
-  const double inv = 1.0 / r;
-  if (lead) a.Rout[(w - 1) + (int64_t)(w - 1) * a.ldr] = r;
-  if (g == 0)
-    for (int e = tid; e < w * w; e += kColThreads) {
-      const int i = e % w, c = e / w;
-      if (i > c) a.Rout[i + (int64_t)c * a.ldr] = 0.0;
-    }
-  for (int64_t r = r0 + tid; r < r1; r += kColThreads) P[r + (w - 1) * ld] *= inv;
 }
 
-// The launches of one leaf: 2w + 2 for CGS2 / ICGS, w + 1 for MGS.  The slab
-// height keeps a workgroup at one or more rows per thread, on at most
-// kColGridMax workgroups.
+// The launches of one leaf: 2w + 2 for CGS2 / ICGS, w + 1 for MGS.  One row
+// per thread while the rows fit kColGridMax workgroups, more beyond.
 void launch_colpanel(const ColArgs& a, hipStream_t st) {
   const int G = (int)std::min<int64_t>(kColGridMax, std::max<int64_t>(1, (a.mrows + kColThreads - 1) / kColThreads));
   const int64_t rb = (a.mrows + G - 1) / G;
   int par = 0;
-  auto go = [&](int kind, int j) {
-    hipLaunchKernelGGL(colgrid_kernel, dim3(G), dim3(kColThreads), 0, st, a, G, rb, kind, j, par);
+  auto go = [&](auto kern, int j) {
+    hipLaunchKernelGGL(kern, dim3(G), dim3(kColThreads), 0, st, a, G, rb, j, par);
     par ^= 1;
   };
   if (a.mode == COLWISE_MGS) {
-    for (int i = 0; i < a.w; ++i) go(CG_MGS, i);
+    for (int i = 0; i < a.w; ++i) go(colgrid_kernel<CG_MGS>, i);
   } else {
-    go(CG_START, 0);
+    go(colgrid_kernel<CG_START>, 0);
     for (int j = 0; j < a.w; ++j) {
-      go(CG_PROJECT, j);
-      go(CG_REORTH, j);
+      go(colgrid_kernel<CG_PROJECT>, j);
+      go(colgrid_kernel<CG_REORTH>, j);
     }
   }
-  go(CG_FINISH, a.w - 1);
+  go(colgrid_kernel<CG_FINISH>, a.w - 1);
 }
 
 CholArgs chol_args(const double* W, int64_t ldw, int w, int pass, double* Rout, int64_t ldr, const double* X,

@@ -162,7 +162,7 @@ struct CholArgs {
 // of the method on every slab, leaving per-workgroup partial sums (kColSlots
 // each) that every workgroup of the next launch reduces in the same order.
 enum : int { COLWISE_CGS2 = 0, COLWISE_ICGS = 1, COLWISE_MGS = 2 };
-constexpr int kColGridMax = 128;
+constexpr int kColGridMax = 256;
 constexpr int kColSlots = 68;       // 64 inner products, three squared norms, one spare
 // partial sums (two buffers, alternating by launch) and four state words
 constexpr int64_t kColWorkDoubles = 2 * (int64_t)kColGridMax * kColSlots + 4;

@@ -69,14 +69,16 @@ def test_columnwise_panels_match_oracle(cqr, mode, sid, n, pr, K, b, storage):
     assert m["residual"] <= 1e-12 and m["orth_coded"] <= 1e-12
 
 
+@pytest.mark.parametrize("m", [40000, 60000], ids=["one_row_per_thread", "two_rows_per_thread"])
 @pytest.mark.parametrize("mode", sorted(MODES))
-def test_columnwise_panels_on_the_widest_grid(cqr, mode):
-    """A tall panel (m' = 50000 rows: 16 x 1 grid of 2500-row blocks, K_v = 4
-    out-of-node, no horizontal code, n = 192, b = 64, one failure) spreads
-    each leaf over the most workgroups the column-wise kernel takes, with a
-    last slab shorter than the others, against the oracle's panel of the same
-    name."""
-    m, n, pr, K, b = 40000, 192, 16, 4, 64
+def test_columnwise_panels_on_the_widest_grid(cqr, mode, m):
+    """Tall panels (16 x 1 grid, K_v = 4 out-of-node, no horizontal code,
+    n = 192, b = 64, one failure) whose leaves take the column-wise kernel's
+    widest grids: m' = 50000 rows (196 workgroups, one row per thread, a
+    short last slab) and m' = 75000 (the 256-workgroup cap, two row blocks
+    per thread, the second one partly empty), against the oracle's panel of
+    the same name."""
+    n, pr, K, b = 192, 16, 4, 64
     A, v, _, lay = make_inputs(n, pr, K, b, "out", seed=3, m=m, pc=1, kh=0)
     sched = synth.draw_schedule("random", n // b, pr, 1, 3, nfail=1)
     print(f"[case] panel {mode} m'={lay.mp} n={n}, schedule {sched}", flush=True)
