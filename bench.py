@@ -785,9 +785,9 @@ def kernel_of(phase: str, b: int, leg: str) -> str:
         # (>= 256 of them): the 128 x 128-tile form
         k = "nnq_kernel<0>"
     if phase == "trailing_product" and b > 64:
-        # panels of several tile rows: 128 x 128 per workgroup in FP64, two
-        # tile rows per workgroup for the FP32 product
-        k = "tnq_kernel<0>" if leg != "fp32" else "tn2_kernel<0, true>"
+        # panels of several tile rows: 128 x 128 per workgroup, in FP64, in
+        # FP32 (FP32 slabs in LDS) or as split-BF16 products
+        k = {"fp64": "tnq_kernel<0>", "fp32": "tnf_kernel", "bf16x3": "tnb_kernel<0>"}[leg]
     elif phase == "trailing_product" and leg == "fp32":
         k = k.replace("<0, false>", "<0, true>")
     return k

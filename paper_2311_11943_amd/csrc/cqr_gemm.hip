@@ -27,6 +27,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ v4d mfma(double x, double y, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
@@ -702,6 +703,152 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   }
 }
 
+// FP32 form of tnq_kernel (the mixed-precision coefficient product
+// R_bar = Qbar^T Q_t): 128 x 128 output per 512-thread workgroup, each wave a
+// 64 x 32 block.  The operands are rounded to FP32 once, as they are staged,
+// and LDS holds FP32 slabs of 32 k-values (72 KB; SK / 2 threads stage one
+// column's slab, one 16-byte pair each).  Each 16 k-values are summed in FP32
+// on v_mfma_f32_16x16x4_f32 and then added into the FP64 accumulators.  The
+// accumulators of both precisions take more than 128 registers: one
+// workgroup per CU.  Alone, at K = 49152 with 256 rows and 32768 columns:
+// ~93 TFLOP/s, against ~69 when every wave rounded the FP64 operands it read
+// from LDS.  K a multiple of 32; output contract of tnq_kernel in the FP32
+// result layout.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void tnf_kernel(TnArgs a) {
+  constexpr int SK = 32, LW = SK + 4, TPC = SK / 2, CPP = 512 / TPC, NQ = 128 / CPP;
+  if (a.prio) __builtin_amdgcn_s_setprio(2);
+  __shared__ float sA[2][128 * LW];
+  __shared__ float sB[2][128 * LW];
+  const int tilesM = a.ntiles / a.tilesN;
+  const int qm = (tilesM + 1) / 2;
+  const int tp = blockIdx.x % qm, tq = blockIdx.x / qm, split = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+  const int wi = wave & 1, wj = wave >> 1;
+  const int ia0 = 64 * wi, jb0 = 32 * wj;
+  const int64_t kb = (int64_t)split * a.kchunk;
+  const int64_t ke = std::min<int64_t>(a.K, kb + a.kchunk);
+  const int lc = tid / TPC, lq = tid % TPC;
+  const double* ga[NQ];
+  const double* gb[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = tp * 128 + lc + CPP * q, j = tq * 128 + lc + CPP * q;
+    // columns outside the matrix read column 0 and feed only unstored outputs
+    ga[q] = a.A + (int64_t)(i < a.M ? i : 0) * a.lda + 2 * lq;
+    gb[q] = a.B + (int64_t)(j < a.N ? j : 0) * a.ldb + 2 * lq;
+  }
+  v4d acc[4][2];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0, 0, 0, 0};
+  auto compute = [&](int buf) {
+    // per 16 k-values: lane group g supplies k-values kk + 4 g .. + 4
+#pragma unroll
+    for (int kk = 0; kk < SK; kk += 16) {
+      v4f t[4][2];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) t[x][y] = v4f{0, 0, 0, 0};
+#pragma unroll
+      for (int s0 = 0; s0 < 4; s0 += 2) {
+        float fa[4][2], fb[2][2];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const v2f v = *reinterpret_cast<const v2f*>(&sA[buf][(ia0 + 16 * x + li) * LW + kk + 4 * g + s0]);
+          fa[x][0] = v.x; fa[x][1] = v.y;
+        }
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const v2f v = *reinterpret_cast<const v2f*>(&sB[buf][(jb0 + 16 * y + li) * LW + kk + 4 * g + s0]);
+          fb[y][0] = v.x; fb[y][1] = v.y;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) t[x][y] = mfma(fb[y][s], fa[x][s], t[x][y]);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) widen_add(acc[x][y], t[x][y]);
+    }
+  };
+  v2d ra[NQ], rb[NQ];
+  auto load = [&](int64_t k) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ra[q] = *reinterpret_cast<const v2d*>(ga[q] + k);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rb[q] = *reinterpret_cast<const v2d*>(gb[q] + k);
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      *reinterpret_cast<v2f*>(&sA[buf][(lc + CPP * q) * LW + 2 * lq]) = v2f{(float)ra[q].x, (float)ra[q].y};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      *reinterpret_cast<v2f*>(&sB[buf][(lc + CPP * q) * LW + 2 * lq]) = v2f{(float)rb[q].x, (float)rb[q].y};
+  };
+  const int nfull = (int)((ke - kb) / SK);
+  if (nfull > 0) {
+    load(kb);
+    put(0);
+    __syncthreads();
+    for (int sl = 0; sl < nfull; ++sl) {
+      if (sl + 1 < nfull) load(kb + (int64_t)(sl + 1) * SK);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(sl & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (sl + 1 < nfull) put((sl + 1) & 1);
+      __syncthreads();
+    }
+  }
+  // the wave's two quadrants of tile (tm, tn), in tn_lds_kernel's layout
+  const int tm = 2 * tp + wi, tn = 2 * tq + (wj >> 1), ch = wj & 1;
+  if (tm >= tilesM || tn >= a.tilesN) return;
+  const int tile = tm * a.tilesN + tn;
+#pragma unroll
+  for (int xh = 0; xh < 2; ++xh) {
+    const int quadrant = xh + 2 * ch;
+    if (a.nsplit > 1) {
+      double* mine = a.part + part_off(split, a.ntiles, tile, quadrant);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine[((x * 2 + y) * 4 + r) * 64 + lane] = acc[2 * xh + x][y][r];
+    } else {
+      // one 16 x 16 block at a time (its C2 loads issued before its stores)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int i = tm * 64 + 32 * xh + 16 * x + li;
+          const int j0 = tn * 64 + 32 * ch + 16 * y;
+          double old[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + colsub(r, g, true);
+            old[r] = (a.C2 && i < a.M2 && j < a.N) ? a.C2[i + (int64_t)j * a.ldc2] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + colsub(r, g, true);
+            const double v = acc[2 * xh + x][y][r];
+            if (i < a.M && j < a.N) {
+              a.C[i + (int64_t)j * a.ldc] = v;
+              if (a.C2 && i < a.M2) a.C2[i + (int64_t)j * a.ldc2] = old[r] + v;
+            }
+          }
+        }
+    }
+  }
+}
+
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -992,9 +1139,10 @@ TnArgs tn_setup(const double* A, int64_t lda, const double* B, int64_t ldb, int 
   // two tile rows per workgroup from two tile rows and four tile columns on
   // (with fewer tile columns the re-projections on the panel chain slow down)
   const bool pair = vec && tilesM >= 2 && tilesN >= 4;
-  // FP64 products of at least two tile rows and columns: 128 x 128 per workgroup
+  // products of at least two tile rows and columns: 128 x 128 per workgroup
   // and a depth that is a multiple of 16 (whole slabs in every split)
-  const bool quad = vec && !f32 && tilesM >= 2 && tilesN >= 2 && K % 16 == 0;
+  // (32 for FP32 products, whose slabs are 32 deep)
+  const bool quad = vec && tilesM >= 2 && tilesN >= 2 && K % (f32 ? 32 : 16) == 0;
   // the split-BF16 product on the same 128 x 128 tiles
   const bool bf3 = vec && lowp == 2 && tilesM >= 2 && tilesN >= 2 && K % 32 == 0;
   // the split count fills the grid of workgroups the product launches
@@ -1030,6 +1178,10 @@ void launch_tn_product(const TnArgs& a, int tag, hipStream_t st) {
   }
   if (a.quad) {
     const dim3 gridq((unsigned)((a.ntiles / a.tilesN + 1) / 2 * ((a.tilesN + 1) / 2)), a.nsplit);
+    if (a.f32) {
+      hipLaunchKernelGGL(tnf_kernel, gridq, dim3(512), 0, st, a);
+      return;
+    }
     switch (tag) {
       case TAG_TRAIL: hipLaunchKernelGGL((tnq_kernel<TAG_TRAIL>), gridq, dim3(512), 0, st, a); break;
       case TAG_REPROJ: hipLaunchKernelGGL((tnq_kernel<TAG_REPROJ>), gridq, dim3(512), 0, st, a); break;
