@@ -299,8 +299,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 
 // The same product with 16-deep slabs (36 KB of LDS, three waves per SIMD),
 // taken by FP32 products with at least two tile rows and two or three tile
-// columns (the last trailing products of wider panels; with four or more tile
-// columns, FP32 products take tn2_kernel).  An FP32 MFMA
+// columns whose depth is not a multiple of 32 (tnf_kernel takes the others;
+// with four or more tile columns, such products take tn2_kernel).  An FP32 MFMA
 // takes fewer cycles than the FP64 one, so the FP32 product waits more on its
 // loads and the third wave hides them (the n = 16384 factorization with FP32
 // updates runs 5% faster); in FP64 the twice as many barriers of the shorter
@@ -441,10 +441,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // of B's column lc.  Each wave stores its 32 x 32 quadrant of its own 64 x 64
 // tile with the contract of tn_lds_kernel (a missing second tile row of an
 // odd tilesM stages and computes but stores nothing).
-// Taken by FP32 products with at least two tile rows and four tile columns
-// (the mixed-precision trailing products of panels wider than 64 columns),
-// and by FP64 ones of that shape that tnq_kernel does not take (a depth that
-// is not a multiple of 16).  Alone, the K = 49152, 256 x 32768 FP64 product
+// Taken by the products with at least two tile rows and four tile columns
+// that the 128 x 128 kernels do not take: FP32 ones whose depth is not a
+// multiple of 32 (tnf_kernel) and FP64 ones whose depth is not a multiple of
+// 16 (tnq_kernel).  Alone, the K = 49152, 256 x 32768 FP64 product
 // ran at 63 TFLOP/s on it against 55 for tn_lds_kernel (tnq_kernel: 65-67).
 template <int TAG, bool F32>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void tn2_kernel(TnArgs a) {
