@@ -669,15 +669,23 @@ def main():
                 torch.cuda.synchronize()
                 return a0.elapsed_time(z0) / reps
 
-            def enc():
+            def copy_in():
                 At[:n, :n].copy_(A)
+
+            def enc():
+                copy_in()
                 q.encode(At)
 
-            t_enc = timed(enc)
-            t_fac = timed(lambda: (enc(), q.factor(At, R))) - t_enc
+            # the factorization overwrites A~, so each timed factorization
+            # starts from a fresh copy of A and its encoding; T_enc is the
+            # encoding alone (the input copy timed on its own and subtracted)
+            t_copy = timed(copy_in)
+            t_enc_in = timed(enc)
+            t_enc = t_enc_in - t_copy
+            t_fac = timed(lambda: (enc(), q.factor(At, R))) - t_enc_in
             t_post = timed(lambda: q.postorth(At, Qpost, B, Bpost))
             L["overhead"] = {"T_enc_ms": round(t_enc, 4), "T_factor_coded_ms": round(t_fac, 4),
-                             "T_post_ms": round(t_post, 4)}
+                             "T_post_ms": round(t_post, 4), "T_input_copy_ms": round(t_copy, 4)}
             if li == 0:
                 # coded solve R_1 x = (G_0 Q_1)^T (G_0 b) on the last step's factors
                 X = cqr.col_major(n, 1, dev)
