@@ -6,6 +6,9 @@
   orthogonality (1e-12), with and without failures, on a tall panel whose
   leaves take the kernel's widest grid (a ragged last slab), and the paper's
   method (MGS panel, no re-projection) at the n = 4096 workload's shape.
+- The ICGS test taken both ways: at eta = 0.97 (most columns, not all,
+  re-orthogonalised by the oracle) element by element, and with a nearly
+  dependent pair in one panel, bounded against the oracle's orthogonality.
 - A panel with two nearly dependent columns (one 1e-9 from another,
   cond(A) ~ 1e11): the Cholesky-QR panel breaks down and the column-wise
   CGS2 fallback takes the panel; the result is bounded by backward error
@@ -96,6 +99,44 @@ def test_columnwise_panels_on_the_widest_grid(cqr, mode, m):
     print(f"    R {rel(Rg, ref['R']):.2e} Q {rel(Qg, ref['Q']):.2e} residual {res:.2e} orth {orth:.2e}", flush=True)
     assert rel(Rg, ref["R"]) <= 1e-11 and rel(Qg, ref["Q"]) <= 1e-11
     assert res <= 1e-12 and orth <= 1e-12
+
+
+@pytest.mark.parametrize("eta,pair", [(0.97, None), (2 ** -0.5, (140, 170))], ids=["eta0.97", "dependent_pair"])
+def test_icgs_reorthogonalises_where_the_oracle_does(cqr, eta, pair):
+    """The ICGS test (second projection when ||p_j|| < eta ||p_j before||)
+    taken both ways: at eta = 0.97 the oracle re-orthogonalises some columns
+    of every panel and not others, and the GPU's R and Q~ must match it
+    element by element; with the default eta and a column 1e-9 from another of
+    its panel, the second projection is what keeps Q~ orthogonal, so residual
+    and orthogonality are bounded against the oracle's (backward error)."""
+    n, pr, K, b = 512, 8, 2, 64
+    A, v, gh, lay = make_inputs(n, pr, K, b, "in", seed=21)
+    A = A.copy()
+    if pair:
+        A[:, pair[1]] = A[:, pair[0]] + 1e-9 * np.random.default_rng(2).standard_normal(n)
+    print(f"[case] icgs eta {eta:.3f} pair {pair}", flush=True)
+    q = cqr.CodedQR(gpu_config(cqr, lay, b, panel=MODES["icgs"], icgs_eta=eta), v, gh)
+    At, R, _, _ = q.run(cqr.to_device_colmajor(A, "cuda:0"), [])
+    torch.cuda.synchronize()
+    assert q.info() == 0
+    Qg, Rg = host(At), host(R)
+    q.close()
+    opt = oc.FactorOptions(b, "icgs", eta=eta)
+    gv, ghm = oc.q_generator(v), oc.r_generator(gh, lay.storage)
+    Q = oc.encode(A, gv, ghm, lay)
+    Ro = np.zeros((lay.n, lay.N))
+    nre = oc.factor_panels(Q, Ro, lay.n, 0, n // b, opt)["reorth_columns"]
+    mg = oc.metrics(A, {"Q": Qg, "R": Rg}, lay)
+    mo = oc.metrics(A, {"Q": Q, "R": Ro}, lay)
+    print(f"    oracle re-orthogonalised {nre} of {lay.n} columns; R {rel(Rg, Ro):.2e} Q {rel(Qg, Q):.2e}\n"
+          f"    GPU {mg}\n    oracle {mo}", flush=True)
+    assert 0 < nre < lay.n
+    if pair is None:
+        assert rel(Rg, Ro) <= 1e-11 and rel(Qg, Q) <= 1e-11
+        assert mg["residual"] <= 1e-12 and mg["orth_coded"] <= 1e-12
+    else:
+        assert mg["residual"] <= 1e-12
+        assert mg["orth_coded"] <= max(1e-12, 4 * mo["orth_coded"])
 
 
 def test_paper_method_mgs_without_reprojection(cqr):
