@@ -1,25 +1,22 @@
-// Column-wise Gram-Schmidt on one panel of w <= 64 columns, in place, by one
-// workgroup: the classical Gram-Schmidt with reorthogonalisation (CGS2: every
-// column projected twice against the finished columns; ICGS: the second
-// projection only when the first shrank the column below eta times its norm,
-// the Daniel-Gragg-Kaufman-Stewart test) and the modified Gram-Schmidt of the
-// paper's sequential MGS algorithm (each new basis vector removed at once from
-// every column to its right).  Norms, coefficients and R are FP64.
+// Column-wise Gram-Schmidt helpers.
 //
-// The panel stays in global memory (L2); thread t owns rows t, t + NT, ...
-// of every column, so each pass over the panel reads whole 512-byte row
-// segments per wave and column.  Inner products against many columns run in
-// chunks of 16 columns (16 accumulators per thread) with one workgroup
-// reduction per chunk: a transposing butterfly inside each wavefront (after
-// four exchange steps lane l holds its lane group's sum for column l mod 16),
-// two more exchanges across the lane groups, and a fixed-order sum over the
-// waves in LDS, so results do not depend on scheduling.  Normalisation of
-// column j is folded into the first pass of column j + 1.
+// colwise_panel: the classical Gram-Schmidt with reorthogonalisation (CGS2:
+// every column projected twice against the finished columns) on one panel of
+// w <= 64 columns, in place, by one workgroup; the second Cholesky-QR pass
+// falls back to it when a Cholesky factorization breaks down.  Norms,
+// coefficients and R are FP64.  The panel stays in global memory (L2); thread
+// t owns rows t, t + NT, ... of every column, so each pass over the panel
+// reads whole 512-byte row segments per wave and column.  Inner products
+// against many columns run in chunks of 16 columns (16 accumulators per
+// thread) with one workgroup reduction per chunk.  Normalisation of column j
+// is folded into the first pass of column j + 1.
 //
-// colwise_panel is the second Cholesky-QR pass's fallback when a Cholesky
-// factorization breaks down (one workgroup, column-wise CGS2);
-// colwise_wave_sum16 also serves colgrid_kernel, the multi-workgroup form of
-// the CGS2 / ICGS / MGS panel modes.
+// colwise_wave_sum16 / colwise_block_sum: the reductions -- a transposing
+// butterfly inside each wavefront (after four exchange steps lane l holds its
+// lane group's sum for column l mod 16), two more exchanges across the lane
+// groups, and (for the workgroup sum) a fixed-order sum over the waves in
+// LDS, so results do not depend on scheduling.  colgrid_kernel, the
+// multi-workgroup CGS2 / ICGS / MGS panel modes, uses the wavefront part.
 #pragma once
 #include "cqr_kernels.hpp"
 
@@ -110,93 +107,50 @@ __device__ __forceinline__ void colwise_dots(double* P, int64_t ldp, int64_t mro
   colwise_block_sum<NT>(acc, n2, c1 - c0, out + c0, nrm, L.red);
 }
 
-// Orthonormalise P (mrows x w, ld ldp, w <= 64) in place; the triangular
-// factor goes to Rl (row-major, zero below the diagonal, zero-padded to
-// 64 x 64).  Returns false if a column has zero (or non-finite) norm after
-// projection: the panel is exactly rank-deficient, and that column is left
-// unnormalised.
+// Orthonormalise P (mrows x w, ld ldp, w <= 64) in place by CGS2; the
+// triangular factor goes to Rl (row-major, zero below the diagonal,
+// zero-padded to 64 x 64).  Returns false if a column has zero (or
+// non-finite) norm after projection: the panel is exactly rank-deficient, and
+// that column is left unnormalised.
 template <int NT>
-__device__ bool colwise_panel(double* P, int64_t ldp, int64_t mrows, int w, int mode, double eta,
-                              double (*Rl)[kLeaf + 1], ColwiseLds<NT>& L) {
+__device__ bool colwise_panel(double* P, int64_t ldp, int64_t mrows, int w, double (*Rl)[kLeaf + 1],
+                              ColwiseLds<NT>& L) {
   const int tid = threadIdx.x;
   bool ok = true;
   for (int e = tid; e < kLeaf * kLeaf; e += NT) Rl[e >> 6][e & 63] = 0.0;
   __syncthreads();
   double none[kColChunk];
-  if (mode == COLWISE_MGS) {
-    // r_00^2 = ||u_0||^2
-    colwise_dots<NT>(P, ldp, mrows, 0, 0, P, L.s1, &L.s1[kLeaf], -1, 1.0, L);
-    double rii2 = L.s1[kLeaf];
-    for (int i = 0; i < w; ++i) {
-      if (!(rii2 > 0.0) || !isfinite(rii2)) { ok = false; rii2 = 1.0; }
-      const double rii = sqrt(rii2);
-      // q_i = u_i / r_ii; r_ic = q_i^T u_c for every c > i
-      double* qi = P + (int64_t)i * ldp;
-      for (int64_t r = tid; r < mrows; r += NT) qi[r] /= rii;
-      __syncthreads();
-      for (int c0 = i + 1; c0 < w; c0 += kColChunk)
-        colwise_dots<NT>(P, ldp, mrows, c0, min(w, c0 + kColChunk), qi, L.s1, nullptr, -1, 1.0, L);
-      if (tid == 0) Rl[i][i] = rii;
-      if (tid > i && tid < w) Rl[i][tid] = L.s1[tid];
-      // u_c -= r_ic q_i for every c > i; ||u_{i+1}||^2 for the next step
-      double nx = 0.0;
-      for (int64_t r = tid; r < mrows; r += NT) {
-        const double q = qi[r];
-        for (int c = i + 1; c < w; ++c) {
-          const double u = P[r + c * ldp] - L.s1[c] * q;
-          P[r + c * ldp] = u;
-          if (c == i + 1) nx += u * u;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kColChunk; ++c) none[c] = 0.0;
-      colwise_block_sum<NT>(none, nx, 0, L.s2, &L.s2[kLeaf], L.red);
-      rii2 = L.s2[kLeaf];
-    }
-    return ok;
-  }
-  // CGS2 / ICGS: column j against the finished columns 0 .. j-1
   double prev_inv = 1.0;    // 1 / r_{j-1, j-1}, applied to column j-1 in column j's first pass
   for (int j = 0; j < w; ++j) {
     double* pj = P + (int64_t)j * ldp;
-    // pass 1: s1 = P[:, <j]^T p_j and ||p_j||^2 (chunk by chunk), column j-1
-    // normalised on the way
+    // pass 1: s1 = P[:, <j]^T p_j (chunk by chunk), column j-1 normalised on the way
     for (int c0 = 0; c0 < max(j, 1); c0 += kColChunk)
-      colwise_dots<NT>(P, ldp, mrows, c0, min(j, c0 + kColChunk), pj, L.s1, c0 == 0 ? &L.s1[kLeaf] : nullptr,
-                       j - 1, prev_inv, L);
-    const double n0 = L.s1[kLeaf];
-    // pass 2: p_j -= P s1, ||p_j||^2
-    double n1 = 0.0;
+      colwise_dots<NT>(P, ldp, mrows, c0, min(j, c0 + kColChunk), pj, L.s1, nullptr, j - 1, prev_inv, L);
+    // pass 2: p_j -= P s1
     for (int64_t r = tid; r < mrows; r += NT) {
       double x = pj[r];
       for (int c = 0; c < j; ++c) x -= P[r + c * ldp] * L.s1[c];
       pj[r] = x;
-      n1 += x * x;
+    }
+    __syncthreads();
+    // pass 3: s2 = P[:, <j]^T p_j; pass 4: p_j -= P s2, ||p_j||^2
+    if (j > 0)
+      for (int c0 = 0; c0 < j; c0 += kColChunk)
+        colwise_dots<NT>(P, ldp, mrows, c0, min(j, c0 + kColChunk), pj, L.s2, nullptr, -1, 1.0, L);
+    double n2 = 0.0;
+    for (int64_t r = tid; r < mrows; r += NT) {
+      double x = pj[r];
+      for (int c = 0; c < j; ++c) x -= P[r + c * ldp] * L.s2[c];
+      pj[r] = x;
+      n2 += x * x;
     }
 #pragma unroll
     for (int c = 0; c < kColChunk; ++c) none[c] = 0.0;
-    colwise_block_sum<NT>(none, n1, 0, L.s2, &L.s2[kLeaf], L.red);
+    colwise_block_sum<NT>(none, n2, 0, L.s2, &L.s2[kLeaf], L.red);
     double rjj2 = L.s2[kLeaf];
-    const bool second = j > 0 && (mode == COLWISE_CGS2 || rjj2 < eta * eta * n0);
-    if (second) {
-      // pass 3: s2 = P[:, <j]^T p_j; pass 4: p_j -= P s2, ||p_j||^2
-      for (int c0 = 0; c0 < j; c0 += kColChunk)
-        colwise_dots<NT>(P, ldp, mrows, c0, min(j, c0 + kColChunk), pj, L.s2, nullptr, -1, 1.0, L);
-      double n2 = 0.0;
-      for (int64_t r = tid; r < mrows; r += NT) {
-        double x = pj[r];
-        for (int c = 0; c < j; ++c) x -= P[r + c * ldp] * L.s2[c];
-        pj[r] = x;
-        n2 += x * x;
-      }
-#pragma unroll
-      for (int c = 0; c < kColChunk; ++c) none[c] = 0.0;
-      colwise_block_sum<NT>(none, n2, 0, L.s2, &L.s2[kLeaf], L.red);
-      rjj2 = L.s2[kLeaf];
-    }
     if (!(rjj2 > 0.0) || !isfinite(rjj2)) { ok = false; rjj2 = 1.0; }
     const double rjj = sqrt(rjj2);
-    if (tid < j) Rl[tid][j] = second ? L.s1[tid] + L.s2[tid] : L.s1[tid];
+    if (tid < j) Rl[tid][j] = L.s1[tid] + L.s2[tid];
     if (tid == 0) Rl[j][j] = rjj;
     prev_inv = 1.0 / rjj;
     __syncthreads();

@@ -1575,7 +1575,7 @@ __device__ void colwise_product_store(double* P, int64_t ldp, int64_t mrows, int
 // Returns false for a zero column (exact rank deficiency).
 __device__ __attribute__((noinline)) bool chol_fallback(const CholArgs& a, double (*Rl)[kLeaf + 1],
                                                         ColwiseLds<256>* L) {
-  const bool ok = colwise_panel<256>(a.P, a.ldp, a.mrows, a.w, COLWISE_CGS2, 0.0, Rl, *L);
+  const bool ok = colwise_panel<256>(a.P, a.ldp, a.mrows, a.w, Rl, *L);
   if (a.X)
     colwise_product_store<256>(a.P, a.ldp, a.mrows, a.w, a.P + (int64_t)a.w * a.ldp, a.ldp, a.w, a.Rbar, a.ldr,
                                *L);
