@@ -1817,7 +1817,15 @@ __global__ __launch_bounds__(kColThreads) void colgrid_kernel(ColArgs a, int G, 
   // not depend on, so the two memory latencies overlap
   const int nit = (int)((rb + kColThreads - 1) / kColThreads);
   colgrid_load_row(v, x0, x1, P, r0, ld, r0 + tid, r0 + tid < r1, lo, hi, e0, e1);
-  const double st0 = state[0], st1 = state[1], st2 = state[2];
+  // the state words a step uses, read before the reduction below (workgroup 0
+  // of the same launch writes only words the step does not read: PROJECT
+  // writes [0] and reads [1], [2]; REORTH writes [1], [2] and reads [0])
+  double st0 = 0.0, st1 = 0.0, st2 = 0.0;
+  if constexpr (kind == CG_REORTH) st0 = state[0];
+  if constexpr (kind == CG_PROJECT || kind == CG_FINISH) {
+    st1 = state[1];
+    st2 = state[2];
+  }
 
   for (int c = tid; c < kLeaf + kColChunk; c += kColThreads) coef[c] = 0.0;
   // reduce the previous launch's partials: its inner products in [rlo, rhi)
