@@ -1755,12 +1755,13 @@ __global__ __launch_bounds__(256) void chol_kernel(CholArgs a) {
 // FINISH normalises the last column.  Workgroup 0 writes R.
 //
 // A thread loads the columns a step touches in its row into registers at
-// once, computes the update and the step's inner products from them, and
-// stores what changed; with one row per thread (up to 65536 rows) a launch
-// waits on memory about three times: the previous partial sums, the row, and
-// the stores.  Partial sums: slots [0, 64) inner products (whole 16-slot
-// chunks are written), 64-66 the squared norms (all three written by every
-// launch).
+// once (the first row block before the reduction of the previous partial
+// sums, so that the two memory latencies overlap), computes the update and
+// the step's inner products from them, and stores what changed; one row per
+// thread up to 65536 rows.  The wavefront sums of every 16-slot chunk are
+// formed first and exchanged through LDS once per row block.  Partial sums:
+// slots [0, 64) inner products (whole 16-slot chunks are written), 64-66 the
+// squared norms (all three written by every launch).
 enum : int { CG_START = 0, CG_PROJECT = 1, CG_REORTH = 2, CG_FINISH = 3, CG_MGS = 4 };
 constexpr int kColThreads = 256;
 constexpr int kSlotNA = 64, kSlotNB = 65, kSlotNC = 66;
