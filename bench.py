@@ -796,7 +796,9 @@ def kernel_of(phase: str, b: int, leg: str) -> str:
         # panels of several tile rows: 128 x 128 per workgroup, in FP64, in
         # FP32 (FP32 slabs in LDS) or as split-BF16 products
         k = {"fp64": "tnq_kernel<0>", "fp32": "tnf_kernel", "bf16x3": "tnb_kernel<0>"}[leg]
-    elif phase == "trailing_product" and leg == "fp32":
+    elif phase == "trailing_product" and leg in ("fp32", "bf16x3"):
+        # one tile row: the FP32 form of the LDS-staged product (the split-BF16
+        # mode takes it too for such products)
         k = k.replace("<0, false>", "<0, true>")
     return k
 
