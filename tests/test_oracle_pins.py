@@ -471,6 +471,44 @@ def test_tall_coded_solve_is_weighted_least_squares():
     assert np.abs(x - xo).max() > 1e-6
 
 
+# ---------------------------------------------------------------- ICGS criterion
+def test_icgs_criterion_reduces_to_cgs_and_cgs2_at_its_limits():
+    """The re-orthogonalization test ||p_j|| < eta ||p_j before|| (reading 4)
+    at its limits and at the default eta = 1/sqrt 2:
+    - eta = 0 never fires: plain classical Gram-Schmidt, which loses
+      orthogonality on a column 1e-9 from another (u kappa);
+    - eta > 1 always fires: bitwise the CGS2 panel;
+    - the default fires on no column of a well-conditioned Gaussian panel and
+      on exactly the nearly dependent column of the other, restoring
+      orthogonality to CGS2's level."""
+    rng = np.random.default_rng(7)
+    gauss = rng.standard_normal((200, 24))
+    dep = gauss.copy()
+    dep[:, 10] = dep[:, 3] + 1e-9 * rng.standard_normal(200)
+
+    def panel(P, reorth, eta):
+        Q, R = P.copy(), np.zeros((24, 24))
+        n = oc.panel_cgs2(Q, R, reorth, eta)
+        return Q, R, n
+
+    def orth(Q):
+        return np.linalg.norm(np.eye(Q.shape[1]) - Q.T @ Q)
+
+    Q, R, n = panel(dep, "dgks", 0.0)
+    assert n == 0 and orth(Q) > 1e-9
+    Qc, Rc, nc = panel(dep, "always", 0.0)
+    assert orth(Qc) < 1e-14
+    for P in (gauss, dep):
+        Q1, R1, n1 = panel(P, "dgks", 1.1)
+        Q2, R2, n2 = panel(P, "always", 0.0)
+        assert n1 == n2 == 24 and np.array_equal(Q1, Q2) and np.array_equal(R1, R2)
+    Q, R, n = panel(gauss, "dgks", oc.ETA_DGKS)
+    assert n == 0
+    Q, R, n = panel(dep, "dgks", oc.ETA_DGKS)
+    assert n == 1 and orth(Q) < 1e-14
+    assert np.linalg.norm(dep - Q @ R) <= 1e-15 * np.linalg.norm(dep)
+
+
 # ---------------------------------------------------------------- planted mistakes
 def test_pins_catch_planted_mistakes(monkeypatch):
     """A wrong sign in the generator construction breaks the post-orth
